@@ -1,0 +1,200 @@
+"""CPU oracle for canonical k-mer counting -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package. The GPU library never uses it.
+
+Thin ctypes wrapper over ``gerbil_oracle.c``; every function's arithmetic is
+in the C file, which cites the passages of the paper it follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gerbil_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (plain C, single-threaded)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", "-O2", "-std=c11", "-shared", "-fPIC", _SRC, "-o", tmp], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("n_valid", ctypes.c_uint64), ("n_valid_shard", ctypes.c_uint64),
+                ("n_distinct", ctypes.c_uint64), ("n_pairs", ctypes.c_uint64),
+                ("keys", ctypes.POINTER(ctypes.c_uint64)), ("counts", ctypes.POINTER(ctypes.c_uint32)),
+                ("hist", ctypes.POINTER(ctypes.c_uint64)), ("hist_len", ctypes.c_uint64),
+                ("max_count", ctypes.c_uint64)]
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+        lib.oracle_count.argtypes = [vp, vp, u64, u32, u32, u32, u64, u64, ctypes.POINTER(_Result)]
+        lib.oracle_count.restype = i32
+        lib.oracle_free.argtypes = [ctypes.POINTER(_Result)]
+        lib.oracle_free.restype = None
+        lib.oracle_count_keys.argtypes = [vp, vp, u64, u32, vp, u64, vp]
+        lib.oracle_count_keys.restype = i32
+        lib.oracle_encode.argtypes = [vp, vp, u64, u32, vp, vp, vp]
+        lib.oracle_encode.restype = i32
+        lib.oracle_supermers.argtypes = [vp, vp, u64, u32, u32, u32, u32, vp, vp, vp, vp, vp, u64, vp]
+        lib.oracle_supermers.restype = i32
+        lib.oracle_shard_of.argtypes = [vp, u32, u64]
+        lib.oracle_shard_of.restype = u64
+        lib.oracle_record.argtypes = [ctypes.c_char_p, u32, u32, vp]
+        lib.oracle_record.restype = u32
+        _lib = lib
+    return _lib
+
+
+def words(k: int) -> int:
+    return (k + 31) // 32
+
+
+def _c(a: np.ndarray, dtype) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+@dataclass
+class Counted:
+    """Oracle result: sorted pairs (count >= threshold) and the full histogram."""
+    k: int
+    n_valid: int            # valid windows of the whole input
+    n_valid_shard: int      # valid windows whose canonical key is in the shard
+    n_distinct: int
+    keys: np.ndarray        # uint64 [n_pairs, W], ascending
+    counts: np.ndarray      # uint32 [n_pairs]
+    hist: np.ndarray        # uint64 [max_count + 1]; hist[c] = #distinct keys with count c
+
+    def folded_hist(self, length: int) -> np.ndarray:
+        """Histogram folded to ``length`` buckets, last bucket = counts >= length-1."""
+        h = np.zeros(length, dtype=np.uint64)
+        n = min(length - 1, self.hist.size)
+        h[:n] = self.hist[:n]
+        if self.hist.size > length - 1:
+            h[length - 1] = self.hist[length - 1:].sum()
+        h[0] = 0
+        return h
+
+
+def count(ascii: np.ndarray, offsets: np.ndarray, k: int, threshold: int = 1, canonical: bool = True,
+          shard_mod: int = 1, shard_id: int = 0) -> Counted:
+    """Sort-and-count of (canonical) k-mers; see ``oracle_count`` in the C file."""
+    lib = _load()
+    a, o = _c(ascii, np.uint8), _c(offsets, np.uint64)
+    r = _Result()
+    rc = lib.oracle_count(a.ctypes.data, o.ctypes.data, o.size - 1, k, threshold, int(canonical),
+                          shard_mod, shard_id, ctypes.byref(r))
+    if rc != 0:
+        raise RuntimeError(f"oracle_count failed with status {rc}")
+    try:
+        W = words(k)
+        n = r.n_pairs
+        keys = np.ctypeslib.as_array(r.keys, shape=(max(n, 1) * W,))[: n * W].reshape(n, W).copy()
+        counts = np.ctypeslib.as_array(r.counts, shape=(max(n, 1),))[:n].copy()
+        hist = np.ctypeslib.as_array(r.hist, shape=(r.hist_len,)).copy() if r.hist_len else \
+            np.zeros(1, dtype=np.uint64)
+        return Counted(k, int(r.n_valid), int(r.n_valid_shard), int(r.n_distinct), keys, counts, hist)
+    finally:
+        lib.oracle_free(ctypes.byref(r))
+
+
+def count_keys(ascii: np.ndarray, offsets: np.ndarray, k: int, query: np.ndarray) -> np.ndarray:
+    """Occurrences of each canonical key in ``query`` ([n, W] uint64)."""
+    lib = _load()
+    W = words(k)
+    q = _c(query, np.uint64).reshape(-1, W)
+    order = np.lexsort(q.T[::-1])
+    qs = np.ascontiguousarray(q[order])
+    out = np.zeros(qs.shape[0], dtype=np.uint64)
+    a, o = _c(ascii, np.uint8), _c(offsets, np.uint64)
+    rc = lib.oracle_count_keys(a.ctypes.data, o.ctypes.data, o.size - 1, k, qs.ctypes.data, qs.shape[0],
+                               out.ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f"oracle_count_keys failed with status {rc}")
+    res = np.empty_like(out)
+    res[order] = out
+    return res
+
+
+def encode(ascii: np.ndarray, offsets: np.ndarray, k: int):
+    """(packed uint64[ceil(n/32)], kmer_ok uint64[ceil(n/64)], n_valid)."""
+    lib = _load()
+    a, o = _c(ascii, np.uint8), _c(offsets, np.uint64)
+    n = int(o[-1])
+    packed = np.zeros((n + 31) // 32, dtype=np.uint64)
+    ok = np.zeros((n + 63) // 64, dtype=np.uint64)
+    nv = np.zeros(1, dtype=np.uint64)
+    rc = lib.oracle_encode(a.ctypes.data, o.ctypes.data, o.size - 1, k, packed.ctypes.data, ok.ctypes.data,
+                           nv.ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f"oracle_encode failed with status {rc}")
+    return packed, ok, int(nv[0])
+
+
+def supermers(ascii: np.ndarray, offsets: np.ndarray, k: int, m: int, n_bins: int, order: int = 0,
+              bin_map: Optional[np.ndarray] = None):
+    """Super-mers as a dict of arrays: start, n_kmers, bin, rank (in read order)."""
+    lib = _load()
+    a, o = _c(ascii, np.uint8), _c(offsets, np.uint64)
+    cap = max(1, int(o[-1]))
+    start = np.empty(cap, dtype=np.uint64)
+    nk = np.empty(cap, dtype=np.uint32)
+    b = np.empty(cap, dtype=np.uint32)
+    rank = np.empty(cap, dtype=np.uint64)
+    n = np.zeros(1, dtype=np.uint64)
+    bm = _c(bin_map, np.uint32) if bin_map is not None else None
+    rc = lib.oracle_supermers(a.ctypes.data, o.ctypes.data, o.size - 1, k, m, order, n_bins,
+                              bm.ctypes.data if bm is not None else None, start.ctypes.data, nk.ctypes.data,
+                              b.ctypes.data, rank.ctypes.data, cap, n.ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f"oracle_supermers failed with status {rc}")
+    c = int(n[0])
+    return {"start": start[:c].copy(), "n_kmers": nk[:c].copy(), "bin": b[:c].copy(), "rank": rank[:c].copy()}
+
+
+def shard_of(keys: np.ndarray, k: int, shard_mod: int) -> np.ndarray:
+    """Shard id of each key row (the oracle's memory-bounding partition)."""
+    lib = _load()
+    W = words(k)
+    ks = _c(keys, np.uint64).reshape(-1, W)
+    out = np.empty(ks.shape[0], dtype=np.uint64)
+    for i in range(ks.shape[0]):
+        out[i] = lib.oracle_shard_of(ks[i].ctypes.data, W, shard_mod)
+    return out
+
+
+def record(kmer: str, count: int) -> bytes:
+    """One output record of the paper's binary format (App. C)."""
+    buf = (ctypes.c_uint8 * (5 + (len(kmer) + 3) // 4))()
+    n = _load().oracle_record(kmer.encode(), len(kmer), count, ctypes.addressof(buf))
+    return bytes(buf[:n])
+
+
+def decode_key(key: np.ndarray, k: int) -> str:
+    """String of a packed key (test helper: inverse of the key layout)."""
+    W = words(k)
+    out = []
+    for i in range(W):
+        nb = 32 if i < W - 1 else k - 32 * (W - 1)
+        w = int(key[i])
+        for j in range(nb):
+            out.append("ACGT"[(w >> (2 * (nb - 1 - j))) & 3])
+    return "".join(out)
