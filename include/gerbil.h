@@ -1,0 +1,232 @@
+/*
+ * gerbil.h -- C ABI of the MI355X (gfx950) k-mer counting library.
+ *
+ * The library implements the counting step of Gerbil (Erbert, Rechner and
+ * Mueller-Hannemann, "Gerbil: A fast and memory-efficient k-mer counter with
+ * GPU-support", arXiv 1607.06618): reads and k go in; canonical (k-mer, count)
+ * pairs above a threshold and the count-of-counts histogram come out
+ * (Sec. 1, problem statement; Sec. 2, two-phase method).
+ *
+ *   gerbil_encode     2-bit encoding of the reads and the table of valid
+ *                     k-mer windows (Sec. 2.3.1 parser step; Sec. 2.4.1:
+ *                     windows with an undetermined base are ignored).
+ *   gerbil_bin        minimizer signatures and super-mers distributed over
+ *                     bins (Sec. 2.1, Fig. 1; Sec. 3.1 ordering; App. A `-f`).
+ *                     The paper's temporary files become device-resident bins.
+ *   gerbil_count      each bin cut into canonical k-mers (Sec. 2.4.2) and
+ *                     counted in open-addressing hash tables with double
+ *                     hashing and at most theta trials (Sec. 2.2, Alg. 1;
+ *                     Sec. 3.3.1 bucket scan; Sec. 3.4.3 emergency area with
+ *                     sort-and-compress); output iff count >= threshold
+ *                     (App. A `-l`).
+ *   gerbil_histogram  number of distinct canonical k-mers per count value.
+ *
+ * Conventions shared by every call
+ *   Memory      Every pointer argument named "device" is device memory owned
+ *               by the caller. The library never allocates or frees device
+ *               memory; workspaces are sized by the *_workspace queries and
+ *               must stay alive (and untouched) while results that point
+ *               into them are used.
+ *   Streams     Calls enqueue work on `stream` (NULL = the default stream)
+ *               and return without waiting, except where a call says it
+ *               synchronises.
+ *   Errors      Argument errors (GERBIL_EINVAL, GERBIL_EUNSUPPORTED) are
+ *               returned before anything is enqueued. Data-dependent capacity
+ *               errors are recorded in a device status word and reported by
+ *               gerbil_result() as GERBIL_ECAPACITY together with the size
+ *               that would have sufficed; results are then incomplete and
+ *               must not be used. Launch failures return GERBIL_EDEVICE.
+ *   Concurrency Calls on different streams with disjoint workspaces may run
+ *               concurrently.
+ *   Key layout  W = ceil(k/32) uint64 words per key; words 0..W-2 hold 32
+ *               bases each with the first base in bits 63:62; word W-1 holds
+ *               the remaining k-32(W-1) bases right-aligned. Bases use the
+ *               2-bit code of App. C (A=0, C=1, G=2, T=3), so numeric order of
+ *               keys (word 0 first) is lexicographic order.
+ */
+#ifndef GERBIL_H
+#define GERBIL_H
+
+#include <hip/hip_runtime_api.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GERBIL_OK = 0,
+    GERBIL_EINVAL = -1,       /* bad argument or workspace too small          */
+    GERBIL_EUNSUPPORTED = -2, /* valid in the paper, not compiled here        */
+    GERBIL_ECAPACITY = -3,    /* a device-side capacity was exceeded          */
+    GERBIL_EDEVICE = -4       /* launch failure or a device wait gave up      */
+} gerbil_status;
+
+/* Counting schedule. PLAIN: one launch sequence per bin, bins in order, the
+ * host reads the bin sizes once. BATCHED: every bin of the run in one
+ * persistent launch with work stealing over bins (no host synchronisation). */
+enum { GERBIL_PLAIN = 0, GERBIL_BATCHED = 1 };
+
+/* Total order on minimizers (Sec. 3.1). KMC2: canonical m-mers in A<C<G<T
+ * order with those starting AAA or ACA moved behind all others. LEX: plain
+ * lexicographic order (Fig. 1). */
+enum { GERBIL_ORDER_KMC2 = 0, GERBIL_ORDER_LEX = 1 };
+
+/* Where hash tables live. AUTO lets the library choose per bin. */
+enum { GERBIL_TABLE_AUTO = 0, GERBIL_TABLE_HBM = 1, GERBIL_TABLE_LDS = 2 };
+
+/* Run parameters; mirrors the command line of App. A. Zero means default. */
+typedef struct {
+    uint32_t k;              /* k-mer length, 2 <= k <= 256 (App. A `-k`: 8..479; longer keys are
+                                GERBIL_EUNSUPPORTED)                                              */
+    uint32_t m;              /* minimizer length, 1 <= m <= 15, m < k (App. A `-m`)              */
+    uint32_t n_bins;         /* number of bins, 1..4096 (App. A `-f`, default 512)               */
+    uint32_t threshold;      /* output iff count >= threshold, >= 1 (App. A `-l`, default 3)     */
+    uint32_t canonical;      /* 1: count canonical k-mers (Sec. 2.4.2). 0 (`-d`) unsupported     */
+    uint32_t order;          /* GERBIL_ORDER_*                                                   */
+    const uint32_t* bin_map; /* device [4^m] canonical m-mer code -> bin, or NULL for
+                                bin = rank mod n_bins                                             */
+    uint32_t mode;           /* GERBIL_PLAIN or GERBIL_BATCHED                                   */
+    uint32_t table;          /* GERBIL_TABLE_*                                                   */
+    float load_factor;       /* target distinct keys per slot, (0, 0.95]; 0 = default 0.5        */
+    uint32_t max_probes;     /* theta of Alg. 1: buckets tried before the emergency path; 0 = 8  */
+    uint32_t block;          /* threads per workgroup for counting, 64..1024; 0 = default        */
+    uint32_t pool;           /* BATCHED: hash tables resident at once; 0 = chosen from budget    */
+    uint64_t overflow_cap;   /* emergency-area capacity in keys; 0 = default                     */
+    uint64_t superm_cap;     /* super-mer descriptor capacity; 0 = default estimate              */
+    uint64_t table_budget;   /* bytes of workspace for hash tables; 0 = default                  */
+} gerbil_params;
+
+/* Output of gerbil_encode. All pointers point into the encode workspace. */
+typedef struct {
+    uint64_t n_reads;
+    uint64_t n_bytes;        /* total ASCII bytes = offsets[n_reads]                  */
+    uint32_t k;
+    uint32_t reserved;
+    uint64_t n_words;        /* ceil(n_bytes / 32) packed words                       */
+    uint64_t n_mask;         /* ceil(n_bytes / 64) bitmask words                      */
+    uint64_t* packed;        /* device [n_words]; packed[-1] and packed[n_words..+1]
+                                exist and are zero. Byte i -> word i/32, bits
+                                63-2(i%32)..62-2(i%32); non-ACGT bytes are code 0     */
+    uint64_t* valid;         /* device bitmask [n_mask+1]: bit i = byte i is ACGT/acgt */
+    uint64_t* read_start;    /* device bitmask [n_mask+1]: bit i = a read starts at i  */
+    uint64_t* kmer_ok;       /* device bitmask [n_mask+1]: bit p = window [p, p+k) is
+                                inside one read and has only valid bases              */
+    uint64_t* n_valid;       /* device scalar: number of valid windows               */
+    uint32_t* status;        /* device scalar: error bits                              */
+} gerbil_encoded;
+
+/* Output of gerbil_bin: super-mers grouped by bin (the temporary files of
+ * Sec. 2.1). A super-mer is stored as a descriptor into the packed reads:
+ * desc = (global position of its first base << 24) | number of k-mers. */
+typedef struct {
+    uint32_t k, m, n_bins, tile;
+    uint64_t cap_superm;     /* capacity of desc                                      */
+    uint64_t n_bytes;
+    const uint64_t* packed;  /* the encoded reads (not owned)                         */
+    uint64_t* desc;          /* device [cap_superm], bin-ordered                      */
+    uint64_t* bin_off;       /* device [n_bins+1]: bin b owns desc[bin_off[b]..bin_off[b+1]) */
+    uint64_t* bin_kmers;     /* device [n_bins]: k-mers per bin                       */
+    uint64_t* n_superm;      /* device scalar: super-mers found (may exceed cap)      */
+    uint32_t* status;        /* device scalar: error bits (shared with the encoding)  */
+} gerbil_bins;
+
+/* State of one gerbil_count call; pointers point into the count workspace. */
+typedef struct {
+    uint32_t k, W, threshold, hist_len;
+    uint64_t cap;            /* capacity of the caller's output arrays (pairs)        */
+    uint64_t overflow_cap;
+    uint64_t* n_out;         /* device scalar: pairs emitted (or needed, if > cap)    */
+    uint64_t* hist;          /* device [hist_len]: internal count-of-counts           */
+    uint64_t* n_overflow;    /* device scalar: k-mer occurrences sent to the emergency area */
+    uint64_t* max_count;     /* device scalar                                         */
+    uint32_t* status;        /* device scalar: error bits                             */
+    uint64_t* n_superm;      /* copied from the bins                                  */
+    uint32_t* bin_status;
+} gerbil_counted;
+
+/* What gerbil_result reads back from the device. */
+typedef struct {
+    uint64_t n_valid;        /* valid windows of the input                            */
+    uint64_t n_superm;       /* super-mers (descriptors needed)                       */
+    uint64_t n_out;          /* pairs emitted (or needed)                             */
+    uint64_t n_overflow;     /* k-mer occurrences that used the emergency area        */
+    uint64_t max_count;      /* largest count seen                                    */
+    uint32_t status;         /* device error bits                                     */
+    uint32_t reserved;
+} gerbil_report;
+
+/* Library version as 0xMMmmpp. */
+uint32_t gerbil_version(void);
+
+/* Static text for a status code. */
+const char* gerbil_status_string(int32_t status);
+
+/* Workspace bytes gerbil_encode needs for n_bytes of ASCII and n_reads reads.
+ * Errors: GERBIL_EINVAL if bytes is NULL or k is out of range. */
+int32_t gerbil_encode_workspace(uint64_t n_reads, uint64_t n_bytes, uint32_t k, uint64_t* bytes);
+
+/* 2-bit encode reads and mark every valid k-mer window (Sec. 2.3.1 parser
+ * step; Sec. 2.4.1 N handling; App. C base code).
+ *   ascii    device uint8 [n_bytes]: concatenated reads (any bytes; only
+ *            A/C/G/T in either case are bases, anything else invalidates the
+ *            windows that contain it)
+ *   offsets  device uint64 [n_reads+1]: read r is ascii[offsets[r], offsets[r+1]);
+ *            offsets[0] = 0, non-decreasing, offsets[n_reads] = n_bytes
+ *   k        window length (2..256)
+ *   ws       device workspace of at least gerbil_encode_workspace() bytes,
+ *            256-byte aligned
+ *   out      host struct filled with pointers into ws
+ * A mismatch between offsets[n_reads] and n_bytes is reported by
+ * gerbil_result (GERBIL_EINVAL). */
+int32_t gerbil_encode(const uint8_t* ascii, const uint64_t* offsets, uint64_t n_reads, uint64_t n_bytes,
+                      uint32_t k, void* ws, uint64_t ws_bytes, gerbil_encoded* out, hipStream_t stream);
+
+/* Workspace bytes gerbil_bin needs. Errors: GERBIL_EINVAL on bad params. */
+int32_t gerbil_bin_workspace(const gerbil_encoded* enc, const gerbil_params* p, uint64_t* bytes);
+
+/* Split the encoded reads into super-mers by minimizer and group them by bin
+ * (Sec. 2.1, Fig. 1; Sec. 3.1; Sec. 2.3.1 splitter step). The minimizer of a
+ * k-mer is its smallest canonical m-mer under the chosen order; a super-mer
+ * is a maximal run of consecutive k-mers with equal minimizers, additionally
+ * cut every `tile` positions. enc must come from gerbil_encode with the same
+ * k and stay alive. Exceeding p->superm_cap is reported as GERBIL_ECAPACITY
+ * by gerbil_result, with the needed count in n_superm. */
+int32_t gerbil_bin(const gerbil_encoded* enc, const gerbil_params* p, void* ws, uint64_t ws_bytes,
+                   gerbil_bins* out, hipStream_t stream);
+
+/* Workspace bytes gerbil_count needs for these bins. SYNCHRONISES: reads the
+ * per-bin k-mer counts from the device to size the hash tables. */
+int32_t gerbil_count_workspace(const gerbil_bins* bins, const gerbil_params* p, uint64_t* bytes);
+
+/* Count the canonical k-mers of every bin (Sec. 2.2, Alg. 1; Sec. 2.3.2;
+ * Sec. 3.3.1; Sec. 3.4) and emit the pairs with count >= p->threshold.
+ *   keys     device uint64 [cap * W]: pair i's key in keys[i*W .. i*W+W-1]
+ *   counts   device uint32 [cap]
+ *   cap      capacity in pairs; n_valid / threshold always suffices
+ *   ws       workspace of gerbil_count_workspace() bytes (256-byte aligned)
+ *   state    host struct filled with pointers into ws (n_out, histogram ...)
+ * Pair order is unspecified. PLAIN mode synchronises once to read the bin
+ * sizes; BATCHED mode does not synchronise. */
+int32_t gerbil_count(const gerbil_bins* bins, const gerbil_params* p, void* ws, uint64_t ws_bytes,
+                     uint64_t* keys, uint32_t* counts, uint64_t cap, gerbil_counted* state, hipStream_t stream);
+
+/* Count-of-counts over every distinct canonical k-mer, before the threshold:
+ * hist[c] = number of k-mers with count c for 1 <= c < len-1, hist[len-1] =
+ * number with count >= len-1, hist[0] = 0.
+ *   hist     device uint64 [len], 2 <= len <= 65536 */
+int32_t gerbil_histogram(const gerbil_counted* state, uint64_t* hist, uint32_t len, hipStream_t stream);
+
+/* Read the device-side counters and status of a finished run. SYNCHRONISES
+ * on `stream`. Any of enc, bins, state may be NULL. Returns GERBIL_OK,
+ * GERBIL_ECAPACITY (a capacity was exceeded; the report holds the needed
+ * sizes), GERBIL_EINVAL (offsets inconsistent) or GERBIL_EDEVICE. */
+int32_t gerbil_result(const gerbil_encoded* enc, const gerbil_bins* bins, const gerbil_counted* state,
+                      gerbil_report* report, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GERBIL_H */

@@ -1,0 +1,482 @@
+// C-ABI of the counting library: argument checks, workspace layout and the
+// launch sequences of gerbil_encode / gerbil_bin / gerbil_count /
+// gerbil_histogram. No device memory is allocated here; every buffer is
+// carved out of a caller-owned workspace.
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/gerbil.h"
+#include "common.h"
+#include "internal.h"
+
+using namespace gerbil;
+
+namespace {
+
+constexpr uint64_t kAlign = 256;
+constexpr uint64_t kHashSeed = 0x243F6A8885A308D3ull;   // digits of pi; only slot positions depend on it
+constexpr uint64_t kDefaultOverflow = 1ull << 20;
+constexpr uint32_t kDefaultTheta = 8;
+constexpr float kDefaultLoad = 0.5f;
+constexpr uint32_t kDefaultBlock = 256;
+
+uint64_t align_up(uint64_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+// Bump allocator over a workspace (or a dry run that only measures).
+struct Carve {
+    uint8_t* base;
+    uint64_t used = 0;
+    explicit Carve(void* b) : base((uint8_t*)b) {}
+    template <typename T>
+    T* take(uint64_t count) {
+        uint64_t off = used;
+        used = align_up(used + count * sizeof(T));
+        return base ? (T*)(base + off) : nullptr;
+    }
+};
+
+uint32_t words_for(uint32_t k) { return (k + 31) / 32; }
+
+int device_cus() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            cus = prop.multiProcessorCount;
+        if (cus <= 0) cus = 256;
+    }
+    return cus;
+}
+
+uint64_t next_pow2(uint64_t x) {
+    uint64_t n = 1;
+    while (n < x) n <<= 1;
+    return n;
+}
+
+// ---------------------------------------------------------------- encode
+struct EncLayout {
+    uint64_t* packed_alloc;
+    uint64_t* valid;
+    uint64_t* read_start;
+    uint64_t* kmer_ok;
+    uint64_t* scalars;   // [0] n_valid, [1] status (as uint32 in the low half)
+};
+
+uint64_t enc_layout(uint64_t n_bytes, void* ws, EncLayout* L) {
+    uint64_t n_words = (n_bytes + 31) / 32, n_mask = (n_bytes + 63) / 64;
+    Carve c(ws);
+    EncLayout l;
+    l.packed_alloc = c.take<uint64_t>(n_words + 3);
+    l.valid = c.take<uint64_t>(n_mask + 1);
+    l.read_start = c.take<uint64_t>(n_mask + 1);
+    l.kmer_ok = c.take<uint64_t>(n_mask + 1);
+    l.scalars = c.take<uint64_t>(4);
+    if (L) *L = l;
+    return c.used;
+}
+
+// ------------------------------------------------------------------ bins
+uint64_t default_superm_cap(uint64_t n_bytes, uint32_t k, uint32_t m) {
+    uint64_t w = k - m + 1;
+    // random minimizers give about 2/(w+1) super-mers per k-mer; allow twice
+    // that, plus one cut per tile
+    uint64_t est = n_bytes * 4 / (w + 1) + n_bytes / kTile + 4096;
+    return std::min<uint64_t>(est, n_bytes + 4096);
+}
+
+struct BinLayout {
+    uint64_t* list_desc;
+    uint32_t* list_bin;
+    uint64_t* desc;
+    uint32_t* bin_count;
+    uint32_t* bin_fill;
+    uint64_t* bin_off;
+    uint64_t* bin_kmers;
+    uint64_t* scalars;   // [0] n_superm
+};
+
+uint64_t bin_layout(uint64_t cap, uint32_t n_bins, void* ws, BinLayout* L) {
+    Carve c(ws);
+    BinLayout l;
+    l.list_desc = c.take<uint64_t>(cap);
+    l.list_bin = c.take<uint32_t>(cap);
+    l.desc = c.take<uint64_t>(cap);
+    l.bin_count = c.take<uint32_t>(n_bins);
+    l.bin_fill = c.take<uint32_t>(n_bins);
+    l.bin_off = c.take<uint64_t>(n_bins + 1);
+    l.bin_kmers = c.take<uint64_t>(n_bins);
+    l.scalars = c.take<uint64_t>(4);
+    if (L) *L = l;
+    return c.used;
+}
+
+int32_t check_params(const gerbil_params* p) {
+    if (!p) return GERBIL_EINVAL;
+    if (p->k < 2 || p->m < 1 || p->m > 15 || p->m >= p->k) return GERBIL_EINVAL;
+    if (p->n_bins < 1 || p->n_bins > kMaxBins) return GERBIL_EINVAL;
+    if (p->threshold < 1) return GERBIL_EINVAL;
+    if (p->order > 1 || p->mode > 1 || p->table > 2) return GERBIL_EINVAL;
+    if (p->load_factor < 0.0f || p->load_factor > 0.95f) return GERBIL_EINVAL;
+    if (p->block && (p->block < 64 || p->block > 1024 || (p->block & 63))) return GERBIL_EINVAL;
+    if (p->k > 32 * GERBIL_MAX_W) return GERBIL_EUNSUPPORTED;
+    if (!p->canonical) return GERBIL_EUNSUPPORTED;
+    return GERBIL_OK;
+}
+
+// ----------------------------------------------------------------- count
+struct CountLayout {
+    uint64_t* scalars;   // [0] n_out [1] n_ovf [2] max_count [3] status
+    uint64_t* hist;
+    uint64_t* ovf_keys;
+    uint64_t* tables;
+};
+
+struct CountSizing {
+    uint32_t W;
+    uint64_t slots;        // per table
+    uint64_t table_bytes;  // per table
+    uint32_t pool;
+    uint64_t ovf_cap;      // power of two
+};
+
+uint64_t slots_for(uint64_t kmers, float load) {
+    // The distinct count of a bin is at most its k-mer count; size for that.
+    double want = (double)kmers / (double)load;
+    uint64_t nb = (uint64_t)(want / kBucket) + 1;
+    if (nb > 0xFFFFFFFFull) nb = 0xFFFFFFFFull;
+    return nb * kBucket;
+}
+
+uint64_t table_bytes(uint64_t slots, uint32_t W) {
+    return align_up(slots * 8) + align_up(slots * 8 * (W - 1)) + align_up(slots * 4);
+}
+
+Table table_at(uint64_t* base, uint64_t slots, uint32_t W) {
+    uint8_t* p = (uint8_t*)base;
+    Table t;
+    t.stride = slots;
+    t.w0 = (uint64_t*)p;
+    p += align_up(slots * 8);
+    t.rest = (uint64_t*)p;
+    p += align_up(slots * 8 * (W - 1));
+    t.cnt = (uint32_t*)p;
+    return t;
+}
+
+uint64_t count_layout(const CountSizing& z, void* ws, CountLayout* L) {
+    Carve c(ws);
+    CountLayout l;
+    l.scalars = c.take<uint64_t>(8);
+    l.hist = c.take<uint64_t>(kHistInternal);
+    l.ovf_keys = c.take<uint64_t>(z.ovf_cap * z.W);
+    l.tables = (uint64_t*)c.take<uint8_t>(z.table_bytes * z.pool);
+    if (L) *L = l;
+    return c.used;
+}
+
+int32_t count_sizing(const gerbil_bins* b, const gerbil_params* p, CountSizing* z) {
+    int32_t st = check_params(p);
+    if (st) return st;
+    if (!b || p->k != b->k || p->n_bins != b->n_bins) return GERBIL_EINVAL;
+    std::vector<uint64_t> kmers(b->n_bins);
+    if (hipDeviceSynchronize() != hipSuccess) return GERBIL_EDEVICE;
+    if (hipMemcpy(kmers.data(), b->bin_kmers, 8 * (size_t)b->n_bins, hipMemcpyDeviceToHost) != hipSuccess)
+        return GERBIL_EDEVICE;
+    uint64_t mx = 1;
+    for (uint64_t v : kmers) mx = std::max(mx, v);
+    float load = p->load_factor > 0 ? p->load_factor : kDefaultLoad;
+    z->W = words_for(p->k);
+    z->slots = slots_for(mx, load);
+    z->table_bytes = table_bytes(z->slots, z->W);
+    z->pool = 1;
+    z->ovf_cap = next_pow2(p->overflow_cap ? p->overflow_cap : kDefaultOverflow);
+    return GERBIL_OK;
+}
+
+int32_t hip_status(hipError_t e) { return e == hipSuccess ? GERBIL_OK : GERBIL_EDEVICE; }
+
+__global__ void k_fold_hist(const uint64_t* __restrict__ hist, uint32_t len, uint64_t* __restrict__ out) {
+    __shared__ uint64_t part[256];
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t c = tid; c + 1 < len; c += blockDim.x) out[c] = c == 0 ? 0ull : hist[c];
+    uint64_t s = 0;
+    for (uint32_t c = len - 1 + tid; c < kHistInternal; c += blockDim.x) s += hist[c];
+    part[tid] = s;
+    __syncthreads();
+    for (uint32_t off = 128; off > 0; off >>= 1) {
+        if (tid < off) part[tid] += part[tid + off];
+        __syncthreads();
+    }
+    if (tid == 0) out[len - 1] = part[0];
+}
+
+}  // namespace
+
+extern "C" {
+
+uint32_t gerbil_version(void) { return 0x000100; }
+
+const char* gerbil_status_string(int32_t s) {
+    switch (s) {
+        case GERBIL_OK: return "ok";
+        case GERBIL_EINVAL: return "invalid argument";
+        case GERBIL_EUNSUPPORTED: return "unsupported parameter";
+        case GERBIL_ECAPACITY: return "device capacity exceeded";
+        case GERBIL_EDEVICE: return "device error";
+    }
+    return "unknown status";
+}
+
+int32_t gerbil_encode_workspace(uint64_t n_reads, uint64_t n_bytes, uint32_t k, uint64_t* bytes) {
+    (void)n_reads;
+    if (!bytes || k < 2 || k > 32 * GERBIL_MAX_W || n_bytes >= (1ull << 40)) return GERBIL_EINVAL;
+    *bytes = enc_layout(n_bytes, nullptr, nullptr);
+    return GERBIL_OK;
+}
+
+int32_t gerbil_encode(const uint8_t* ascii, const uint64_t* offsets, uint64_t n_reads, uint64_t n_bytes, uint32_t k,
+                      void* ws, uint64_t ws_bytes, gerbil_encoded* out, hipStream_t stream) {
+    if (!out || !ws || !offsets || (n_bytes && !ascii)) return GERBIL_EINVAL;
+    if (k < 2 || k > 32 * GERBIL_MAX_W || n_bytes >= (1ull << 40)) return GERBIL_EINVAL;
+    if (((uintptr_t)ws) & (kAlign - 1)) return GERBIL_EINVAL;
+    EncLayout L;
+    if (enc_layout(n_bytes, ws, &L) > ws_bytes) return GERBIL_EINVAL;
+    const uint64_t n_words = (n_bytes + 31) / 32, n_mask = (n_bytes + 63) / 64;
+    memset(out, 0, sizeof(*out));
+    out->n_reads = n_reads;
+    out->n_bytes = n_bytes;
+    out->k = k;
+    out->n_words = n_words;
+    out->n_mask = n_mask;
+    out->packed = L.packed_alloc + 1;
+    out->valid = L.valid;
+    out->read_start = L.read_start;
+    out->kmer_ok = L.kmer_ok;
+    out->n_valid = L.scalars;
+    out->status = (uint32_t*)(L.scalars + 1);
+    hipError_t e = launch_fill_u64(L.scalars, 4, 0, stream);
+    // zero words that no lane of the packing kernel writes: the pads, the last word
+    if (e == hipSuccess) e = launch_fill_u64(L.packed_alloc, 1, 0, stream);
+    if (e == hipSuccess) e = launch_fill_u64(L.packed_alloc + 1 + (n_words ? n_words - 1 : 0), n_words ? 3 : 2, 0, stream);
+    if (e == hipSuccess) e = launch_fill_u64(L.valid + (n_mask ? n_mask - 1 : 0), n_mask ? 2 : 1, 0, stream);
+    if (e == hipSuccess) e = launch_fill_u64(L.read_start, n_mask + 1, 0, stream);
+    if (e == hipSuccess) e = launch_fill_u64(L.kmer_ok + n_mask, 1, 0, stream);
+    if (e == hipSuccess) e = launch_read_starts(offsets, n_reads, n_bytes, L.read_start, out->status, stream);
+    if (n_bytes) {
+        if (e == hipSuccess) e = launch_pack(ascii, n_bytes, out->packed, L.valid, stream);
+        if (e == hipSuccess) e = launch_kmer_ok(L.valid, L.read_start, n_mask, k, L.kmer_ok, out->n_valid, stream);
+    }
+    return hip_status(e);
+}
+
+int32_t gerbil_bin_workspace(const gerbil_encoded* enc, const gerbil_params* p, uint64_t* bytes) {
+    int32_t st = check_params(p);
+    if (st) return st;
+    if (!enc || !bytes || enc->k != p->k) return GERBIL_EINVAL;
+    uint64_t cap = p->superm_cap ? p->superm_cap : default_superm_cap(enc->n_bytes, p->k, p->m);
+    *bytes = bin_layout(cap, p->n_bins, nullptr, nullptr);
+    return GERBIL_OK;
+}
+
+int32_t gerbil_bin(const gerbil_encoded* enc, const gerbil_params* p, void* ws, uint64_t ws_bytes, gerbil_bins* out,
+                   hipStream_t stream) {
+    int32_t st = check_params(p);
+    if (st) return st;
+    if (!enc || !out || !ws || enc->k != p->k) return GERBIL_EINVAL;
+    if (((uintptr_t)ws) & (kAlign - 1)) return GERBIL_EINVAL;
+    uint64_t cap = p->superm_cap ? p->superm_cap : default_superm_cap(enc->n_bytes, p->k, p->m);
+    BinLayout L;
+    if (bin_layout(cap, p->n_bins, ws, &L) > ws_bytes) return GERBIL_EINVAL;
+    memset(out, 0, sizeof(*out));
+    out->k = p->k;
+    out->m = p->m;
+    out->n_bins = p->n_bins;
+    out->tile = kTile;
+    out->cap_superm = cap;
+    out->n_bytes = enc->n_bytes;
+    out->packed = enc->packed;
+    out->desc = L.desc;
+    out->bin_off = L.bin_off;
+    out->bin_kmers = L.bin_kmers;
+    out->n_superm = L.scalars;
+    out->status = enc->status;
+
+    BinArgs a;
+    a.packed = enc->packed;
+    a.kmer_ok = enc->kmer_ok;
+    a.n_bytes = enc->n_bytes;
+    a.k = p->k;
+    a.m = p->m;
+    a.n_bins = p->n_bins;
+    a.order = p->order;
+    a.bin_map = p->bin_map;
+    a.cap = cap;
+    a.list_desc = L.list_desc;
+    a.list_bin = L.list_bin;
+    a.n_superm = L.scalars;
+    a.bin_count = L.bin_count;
+    a.bin_fill = L.bin_fill;
+    a.bin_off = L.bin_off;
+    a.bin_kmers = L.bin_kmers;
+    a.desc = L.desc;
+    a.status = enc->status;
+    hipError_t e = launch_fill_u64(L.scalars, 4, 0, stream);
+    if (e == hipSuccess) e = launch_fill_u32(L.bin_count, p->n_bins, 0, stream);
+    uint64_t n_tiles = (enc->n_bytes + kTile - 1) / kTile;
+    uint64_t g = std::min<uint64_t>(std::max<uint64_t>(n_tiles, 1), (uint64_t)device_cus() * 8);
+    if (e == hipSuccess) e = launch_bin(a, (uint32_t)g, stream);
+    return hip_status(e);
+}
+
+int32_t gerbil_count_workspace(const gerbil_bins* bins, const gerbil_params* p, uint64_t* bytes) {
+    if (!bytes) return GERBIL_EINVAL;
+    CountSizing z;
+    int32_t st = count_sizing(bins, p, &z);
+    if (st) return st;
+    *bytes = count_layout(z, nullptr, nullptr);
+    return GERBIL_OK;
+}
+
+int32_t gerbil_count(const gerbil_bins* bins, const gerbil_params* p, void* ws, uint64_t ws_bytes, uint64_t* keys,
+                     uint32_t* counts, uint64_t cap, gerbil_counted* state, hipStream_t stream) {
+    int32_t st = check_params(p);
+    if (st) return st;
+    if (!bins || !ws || !state || (cap && (!keys || !counts))) return GERBIL_EINVAL;
+    if (p->k != bins->k || p->n_bins != bins->n_bins) return GERBIL_EINVAL;
+    if (((uintptr_t)ws) & (kAlign - 1)) return GERBIL_EINVAL;
+    if (p->mode == GERBIL_BATCHED) return GERBIL_EUNSUPPORTED;
+    const uint32_t W = words_for(p->k);
+    const uint32_t n_bins = bins->n_bins;
+
+    // The plain schedule reads the bin sizes once.
+    std::vector<uint64_t> off(n_bins + 1), kmers(n_bins);
+    uint64_t n_superm = 0;
+    hipError_t e = hipMemcpyAsync(off.data(), bins->bin_off, 8 * (size_t)(n_bins + 1), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(kmers.data(), bins->bin_kmers, 8 * (size_t)n_bins, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&n_superm, bins->n_superm, 8, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return GERBIL_EDEVICE;
+
+    float load = p->load_factor > 0 ? p->load_factor : kDefaultLoad;
+    CountSizing z;
+    z.W = W;
+    uint64_t mx = 1;
+    for (uint64_t v : kmers) mx = std::max(mx, v);
+    z.slots = slots_for(mx, load);
+    z.table_bytes = table_bytes(z.slots, W);
+    z.pool = 1;
+    z.ovf_cap = next_pow2(p->overflow_cap ? p->overflow_cap : kDefaultOverflow);
+    CountLayout L;
+    if (count_layout(z, ws, &L) > ws_bytes) return GERBIL_EINVAL;
+
+    memset(state, 0, sizeof(*state));
+    state->k = p->k;
+    state->W = W;
+    state->threshold = p->threshold;
+    state->hist_len = kHistInternal;
+    state->cap = cap;
+    state->overflow_cap = z.ovf_cap;
+    state->n_out = L.scalars;
+    state->n_overflow = L.scalars + 1;
+    state->max_count = L.scalars + 2;
+    state->status = (uint32_t*)(L.scalars + 3);
+    state->hist = L.hist;
+    state->n_superm = bins->n_superm;
+    state->bin_status = bins->status;
+
+    CountArgs a;
+    a.packed = bins->packed;
+    a.n_bytes = bins->n_bytes;
+    a.desc = bins->desc;
+    a.k = p->k;
+    a.W = W;
+    a.threshold = p->threshold;
+    a.theta = p->max_probes ? p->max_probes : kDefaultTheta;
+    a.seed = kHashSeed;
+    a.ovf_keys = L.ovf_keys;
+    a.ovf_cap = z.ovf_cap;
+    a.n_ovf = state->n_overflow;
+    a.out_keys = keys;
+    a.out_counts = counts;
+    a.cap = cap;
+    a.n_out = state->n_out;
+    a.hist = L.hist;
+    a.max_count = state->max_count;
+    a.status = state->status;
+
+    Table t = table_at(L.tables, z.slots, W);
+    e = launch_fill_u64(L.scalars, 8, 0, stream);
+    if (e == hipSuccess) e = launch_fill_u64(L.hist, kHistInternal, 0, stream);
+    if (e == hipSuccess) e = launch_fill_u64(t.w0, z.slots, GERBIL_EMPTY, stream);
+    if (e == hipSuccess) e = launch_fill_u32(t.cnt, z.slots, 0, stream);
+    if (e != hipSuccess) return GERBIL_EDEVICE;
+    if (n_superm > bins->cap_superm) return GERBIL_OK;   // reported by gerbil_result as ECAPACITY
+
+    const uint32_t block = p->block ? p->block : kDefaultBlock;
+    for (uint32_t b = 0; b < n_bins && e == hipSuccess; b++) {
+        uint64_t d0 = off[b], d1 = off[b + 1];
+        if (d1 <= d0) continue;
+        uint64_t slots = std::min<uint64_t>(slots_for(kmers[b], load), z.slots);
+        uint32_t nb = (uint32_t)(slots / kBucket);
+        e = launch_count_bin(a, t, nb, d0, d1, block, stream);
+        if (e == hipSuccess) e = launch_compact(a, t, nb, stream);
+    }
+    if (e == hipSuccess) e = launch_overflow(a, stream);
+    return hip_status(e);
+}
+
+int32_t gerbil_histogram(const gerbil_counted* state, uint64_t* hist, uint32_t len, hipStream_t stream) {
+    if (!state || !hist || len < 2 || len > kHistInternal || !state->hist) return GERBIL_EINVAL;
+    hipLaunchKernelGGL(k_fold_hist, dim3(1), dim3(256), 0, stream, state->hist, len, hist);
+    return hip_status(hipGetLastError());
+}
+
+int32_t gerbil_result(const gerbil_encoded* enc, const gerbil_bins* bins, const gerbil_counted* state,
+                      gerbil_report* report, hipStream_t stream) {
+    if (!report) return GERBIL_EINVAL;
+    memset(report, 0, sizeof(*report));
+    if (hipStreamSynchronize(stream) != hipSuccess) return GERBIL_EDEVICE;
+    uint32_t status = 0, s32 = 0;
+    if (enc) {
+        if (hipMemcpy(&report->n_valid, enc->n_valid, 8, hipMemcpyDeviceToHost) != hipSuccess) return GERBIL_EDEVICE;
+        if (hipMemcpy(&s32, enc->status, 4, hipMemcpyDeviceToHost) != hipSuccess) return GERBIL_EDEVICE;
+        status |= s32;
+    }
+    if (bins) {
+        if (hipMemcpy(&report->n_superm, bins->n_superm, 8, hipMemcpyDeviceToHost) != hipSuccess) return GERBIL_EDEVICE;
+        if (hipMemcpy(&s32, bins->status, 4, hipMemcpyDeviceToHost) != hipSuccess) return GERBIL_EDEVICE;
+        status |= s32;
+        if (report->n_superm > bins->cap_superm) status |= ST_SUPERM_CAP;
+    }
+    if (state) {
+        if (hipMemcpy(&report->n_out, state->n_out, 8, hipMemcpyDeviceToHost) != hipSuccess) return GERBIL_EDEVICE;
+        if (hipMemcpy(&report->n_overflow, state->n_overflow, 8, hipMemcpyDeviceToHost) != hipSuccess)
+            return GERBIL_EDEVICE;
+        if (hipMemcpy(&report->max_count, state->max_count, 8, hipMemcpyDeviceToHost) != hipSuccess)
+            return GERBIL_EDEVICE;
+        if (hipMemcpy(&s32, state->status, 4, hipMemcpyDeviceToHost) != hipSuccess) return GERBIL_EDEVICE;
+        status |= s32;
+        if (report->n_out > state->cap) status |= ST_OUT_CAP;
+        if (report->n_overflow > state->overflow_cap) status |= ST_OVF_CAP;
+        if (state->bin_status) {
+            if (hipMemcpy(&s32, state->bin_status, 4, hipMemcpyDeviceToHost) != hipSuccess) return GERBIL_EDEVICE;
+            status |= s32;
+        }
+        if (state->n_superm) {
+            uint64_t ns = 0;
+            if (hipMemcpy(&ns, state->n_superm, 8, hipMemcpyDeviceToHost) != hipSuccess) return GERBIL_EDEVICE;
+            if (bins && ns > bins->cap_superm) status |= ST_SUPERM_CAP;
+        }
+    }
+    report->status = status;
+    if (status & (ST_SPIN)) return GERBIL_EDEVICE;
+    if (status & ST_OFFSETS) return GERBIL_EINVAL;
+    if (status & (ST_OUT_CAP | ST_OVF_CAP | ST_SUPERM_CAP | ST_POOL | ST_COUNT_SAT)) return GERBIL_ECAPACITY;
+    return GERBIL_OK;
+}
+
+}  // extern "C"

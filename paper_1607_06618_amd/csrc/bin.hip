@@ -1,0 +1,251 @@
+// Distribution into bins (phase one, Sec. 2.1 and Sec. 2.3.1 splitter step).
+//
+// The minimizer of a k-mer is its smallest m-mer under a total order on
+// m-mers (Sec. 2.1); here the m-mers are canonical (smaller of the m-mer and
+// its reverse complement) so that a k-mer and its reverse complement share a
+// minimizer and therefore a bin. Orders (Sec. 3.1): KMC2-style -- canonical
+// code c, moved behind all others (c + 4^m) when it starts with AAA or ACA --
+// or plain lexicographic. A super-mer is a maximal run of consecutive valid
+// k-mers with equal minimizers (Fig. 1); all of its k-mers go to the bin of
+// that minimizer, so every occurrence of a canonical k-mer lands in one bin
+// (the partition property of Sec. 2.1).
+//
+// GPU design: the read stream is cut into tiles of kTile k-mer start
+// positions. A workgroup computes the m-mer ranks of its tile plus a halo of
+// w = k-m+1 positions, takes the sliding-window minimum over w by doubling
+// in LDS (log2 w steps), finds super-mer starts with wave ballots, and writes
+// one descriptor per super-mer piece (super-mers are also cut at tile
+// boundaries; both pieces keep the same bin). Per-bin super-mer counts are
+// privatised in LDS. A scan and an LDS-privatised scatter then group the
+// descriptors by bin.
+#include "common.h"
+#include "internal.h"
+
+namespace gerbil {
+
+constexpr uint32_t kBinBlock = 256;
+constexpr uint32_t kMaxW = 256;                 // w = k - m + 1 <= 256 for k <= 256
+constexpr uint32_t kRankLen = kTile + kMaxW;    // ranks for positions P0-1 .. P0+kTile-1+w-1
+constexpr uint32_t kWordsPerTile = kTile / 64;
+constexpr uint32_t kRankPerThread = (kRankLen + kBinBlock - 1) / kBinBlock;
+
+// Rank of the canonical m-mer starting at position j.
+__device__ __forceinline__ uint32_t mmer_rank(const uint64_t* __restrict__ P, int64_t j, uint32_t m, uint32_t order) {
+    uint64_t win = window32(P, j);
+    uint64_t fw = win >> (64 - 2 * m);
+    uint64_t rc = revcomp32(win) & ((1ull << (2 * m)) - 1ull);   // last m bases of the reversed window
+    uint64_t c = fw < rc ? fw : rc;
+    if (order == 0 && m >= 3) {
+        uint64_t head = c >> (2 * m - 6);   // first three bases
+        if (head == 0 /* AAA */ || head == 4 /* ACA */) c += 1ull << (2 * m);
+    }
+    return (uint32_t)c;
+}
+
+__global__ void __launch_bounds__(kBinBlock) k_bin_tiles(BinArgs a) {
+    __shared__ uint32_t R[kRankLen];
+    __shared__ uint32_t M[kTile + 1];
+    __shared__ uint64_t brk[kWordsPerTile];
+    __shared__ uint64_t stw[kWordsPerTile];
+    __shared__ uint32_t wpre[kWordsPerTile + 1];
+    __shared__ uint64_t tile_base;
+    extern __shared__ uint32_t bin_cnt[];   // [n_bins]
+
+    const uint32_t tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
+    const uint32_t w = a.k - a.m + 1;
+    const uint64_t n_pos = a.n_bytes;
+    const uint64_t n_tiles = (n_pos + kTile - 1) / kTile;
+    const uint64_t n_mask = (n_pos + 63) >> 6;
+    const uint32_t code_mask = (uint32_t)((1ull << (2 * a.m)) - 1ull);
+
+    for (uint32_t b = tid; b < a.n_bins; b += kBinBlock) bin_cnt[b] = 0;
+
+    for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t P0 = (int64_t)(tile * kTile);
+        const uint32_t len = kTile + w;   // ranks R[i] for positions P0-1+i
+        // 1. ranks
+        for (uint32_t i = tid; i < len; i += kBinBlock) {
+            int64_t j = P0 - 1 + (int64_t)i;
+            R[i] = (j < (int64_t)n_pos) ? mmer_rank(a.packed, j, a.m, a.order) : 0xFFFFFFFFu;
+        }
+        __syncthreads();
+        // 2. sliding minimum over w by doubling: after a step R[i] = min over [i, i+2s)
+        uint32_t span = 1;
+        while (2 * span <= w) {
+            uint32_t v[kRankPerThread];
+#pragma unroll
+            for (uint32_t e = 0; e < kRankPerThread; e++) {
+                uint32_t i = tid + e * kBinBlock;
+                v[e] = 0;
+                if (i + span < len) v[e] = min(R[i], R[i + span]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (uint32_t e = 0; e < kRankPerThread; e++) {
+                uint32_t i = tid + e * kBinBlock;
+                if (i + span < len) R[i] = v[e];
+            }
+            __syncthreads();
+            span *= 2;
+        }
+        // minimizer of the k-mer at P0-1+i covers ranks [i, i+w)
+        for (uint32_t i = tid; i <= kTile; i += kBinBlock) M[i] = min(R[i], R[i + w - span]);
+        __syncthreads();
+        // 3. super-mer starts and ends (ballot per 64 positions)
+        for (uint32_t c = wave; c < kWordsPerTile; c += kBinBlock / 64) {
+            uint64_t q = (uint64_t)(P0 >> 6) + c;
+            uint64_t okw = q < n_mask ? a.kmer_ok[q] : 0ull;
+            uint64_t okprev = (c == 0) ? 0ull : ((q - 1) < n_mask ? a.kmer_ok[q - 1] : 0ull);
+            bool ok = (okw >> lane) & 1ull;
+            bool ok_before = lane ? ((okw >> (lane - 1)) & 1ull) : ((okprev >> 63) & 1ull);
+            uint32_t t = c * 64 + lane;   // position P0 + t, minimizer M[t+1]
+            bool start = ok && (t == 0 || !ok_before || M[t + 1] != M[t]);
+            uint64_t sb = __ballot(start);
+            uint64_t bb = __ballot(!ok || start);
+            if (lane == 0) { stw[c] = sb; brk[c] = bb; }
+        }
+        __syncthreads();
+        if (wave == 0) {
+            uint32_t n = lane < kWordsPerTile ? (uint32_t)__popcll(stw[lane]) : 0u;
+            uint32_t incl = n;
+            for (int off = 1; off < 64; off <<= 1) {
+                uint32_t y = __shfl_up(incl, off);
+                if (lane >= (uint32_t)off) incl += y;
+            }
+            if (lane < kWordsPerTile) wpre[lane] = incl - n;
+            if (lane == kWordsPerTile - 1) {
+                wpre[kWordsPerTile] = incl;
+                tile_base = incl ? add_dev(a.n_superm, (uint64_t)incl) : 0ull;
+            }
+        }
+        __syncthreads();
+        // 4. one descriptor per start
+        for (uint32_t c = wave; c < kWordsPerTile; c += kBinBlock / 64) {
+            uint64_t sw = stw[c];
+            if (!((sw >> lane) & 1ull)) continue;
+            uint32_t t = c * 64 + lane;
+            uint32_t rank = wpre[c] + (uint32_t)__popcll(sw & ((1ull << lane) - 1ull));
+            uint64_t above = (lane == 63) ? 0ull : (brk[c] & ~((2ull << lane) - 1ull));
+            uint32_t end = kTile;
+            if (above) {
+                end = c * 64 + (uint32_t)__builtin_ctzll(above);
+            } else {
+                for (uint32_t d = c + 1; d < kWordsPerTile; d++) {
+                    if (brk[d]) { end = d * 64 + (uint32_t)__builtin_ctzll(brk[d]); break; }
+                }
+            }
+            uint32_t nk = end - t;
+            uint32_t mr = M[t + 1];
+            uint32_t code = mr & code_mask;
+            uint32_t bin = a.bin_map ? a.bin_map[code] : (mr % a.n_bins);
+            if (bin >= a.n_bins) bin = a.n_bins - 1;   // defensive: a bad map must not index out of range
+            uint64_t idx = tile_base + rank;
+            if (idx < a.cap) {
+                a.list_desc[idx] = ((uint64_t)(P0 + t) << 24) | nk;
+                a.list_bin[idx] = bin;
+                atomicAdd(&bin_cnt[bin], 1u);
+            } else {
+                set_status(a.status, ST_SUPERM_CAP);
+            }
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    for (uint32_t b = tid; b < a.n_bins; b += kBinBlock)
+        if (bin_cnt[b]) atomicAdd(&a.bin_count[b], bin_cnt[b]);
+}
+
+// Exclusive prefix of the per-bin super-mer counts (single workgroup).
+__global__ void __launch_bounds__(1024) k_bin_scan(BinArgs a) {
+    __shared__ uint64_t part[1024];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t per = (a.n_bins + 1023) / 1024;
+    uint64_t local[4];
+    uint64_t s = 0;
+    for (uint32_t e = 0; e < per; e++) {
+        uint32_t b = tid * per + e;
+        uint64_t v = b < a.n_bins ? (uint64_t)a.bin_count[b] : 0ull;
+        local[e] = s;
+        s += v;
+    }
+    part[tid] = s;
+    __syncthreads();
+    for (uint32_t off = 1; off < 1024; off <<= 1) {
+        uint64_t y = tid >= off ? part[tid - off] : 0ull;
+        __syncthreads();
+        part[tid] += y;
+        __syncthreads();
+    }
+    uint64_t base = tid ? part[tid - 1] : 0ull;
+    for (uint32_t e = 0; e < per; e++) {
+        uint32_t b = tid * per + e;
+        if (b < a.n_bins) {
+            a.bin_off[b] = base + local[e];
+            a.bin_fill[b] = 0;
+            a.bin_kmers[b] = 0;
+        }
+    }
+    if (tid == 1023) a.bin_off[a.n_bins] = part[1023];
+}
+
+constexpr uint32_t kScatterPer = 16;   // descriptors per thread per chunk
+
+__global__ void __launch_bounds__(kBinBlock) k_bin_scatter(BinArgs a) {
+    extern __shared__ uint32_t sh[];
+    uint32_t* lh = sh;                  // [n_bins] counts in this chunk
+    uint32_t* lk = sh + a.n_bins;       // [n_bins] k-mers in this chunk
+    uint32_t* gb = sh + 2 * a.n_bins;   // [n_bins] global base of this chunk in the bin
+    const uint32_t tid = threadIdx.x;
+    uint64_t n = ld_dev(a.n_superm);
+    if (n > a.cap) n = a.cap;
+    const uint64_t chunk = (uint64_t)kBinBlock * kScatterPer;
+    for (uint64_t c0 = blockIdx.x * chunk; c0 < n; c0 += (uint64_t)gridDim.x * chunk) {
+        for (uint32_t b = tid; b < a.n_bins; b += kBinBlock) { lh[b] = 0; lk[b] = 0; }
+        __syncthreads();
+        uint64_t d[kScatterPer];
+        uint32_t bn[kScatterPer], lr[kScatterPer];
+#pragma unroll
+        for (uint32_t e = 0; e < kScatterPer; e++) {
+            uint64_t i = c0 + tid + (uint64_t)e * kBinBlock;
+            bn[e] = 0xFFFFFFFFu;
+            if (i < n) {
+                d[e] = a.list_desc[i];
+                bn[e] = a.list_bin[i];
+                lr[e] = atomicAdd(&lh[bn[e]], 1u);
+                atomicAdd(&lk[bn[e]], (uint32_t)(d[e] & 0xFFFFFFu));
+            }
+        }
+        __syncthreads();
+        for (uint32_t b = tid; b < a.n_bins; b += kBinBlock) {
+            if (lh[b]) {
+                gb[b] = atomicAdd(&a.bin_fill[b], lh[b]);
+                add_dev(&a.bin_kmers[b], (uint64_t)lk[b]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (uint32_t e = 0; e < kScatterPer; e++) {
+            if (bn[e] == 0xFFFFFFFFu) continue;
+            uint64_t pos = a.bin_off[bn[e]] + gb[bn[e]] + lr[e];
+            if (pos < a.bin_off[bn[e] + 1] && pos < a.cap) a.desc[pos] = d[e];
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_bin(const BinArgs& a, uint32_t grid, hipStream_t s) {
+    size_t sh_tiles = (size_t)a.n_bins * sizeof(uint32_t);
+    hipLaunchKernelGGL(k_bin_tiles, dim3(grid), dim3(kBinBlock), sh_tiles, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    size_t sh_sc = 3 * (size_t)a.n_bins * sizeof(uint32_t);
+    uint64_t chunks = (a.cap + (uint64_t)kBinBlock * kScatterPer - 1) / ((uint64_t)kBinBlock * kScatterPer);
+    uint32_t g = (uint32_t)(chunks < 2048 ? (chunks ? chunks : 1) : 2048);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(g), dim3(kBinBlock), sh_sc, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace gerbil

@@ -1,0 +1,146 @@
+// Device helpers shared by the gfx950 kernels of the counting path.
+//
+// Base code and packing (App. C): A=00, C=01, G=10, T=11. The read stream is
+// packed 32 bases per 64-bit word, byte position i -> word i/32, with the
+// first base of a word in bits 63:62. The packed array is preceded by one and
+// followed by two zero words, so that any 32-base window starting in
+// [-32, n_bytes) can be read without a bounds test.
+//
+// Key layout: W = ceil(k/32) words; words 0..W-2 hold 32 bases each (first
+// base most significant), word W-1 holds the remaining r = k - 32(W-1) bases
+// right-aligned. Numeric comparison word by word from word 0 is then the
+// lexicographic order A<C<G<T used for canonical k-mers (Sec. 2.4.2).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define GERBIL_MAX_W 8          // longest key compiled: 8 words = k <= 256
+#define GERBIL_EMPTY (~(uint64_t)0)    // probe word of an unclaimed slot
+
+// Device status bits (written with atomicOr, read back by the host).
+#define ST_OUT_CAP 0x1u         // output pairs exceeded the caller's capacity
+#define ST_OVF_CAP 0x2u         // emergency area exceeded its capacity
+#define ST_SUPERM_CAP 0x4u      // super-mer descriptors exceeded capacity
+#define ST_COUNT_SAT 0x8u       // a counter reached 2^32-1
+#define ST_SPIN 0x10u           // a bounded wait gave up (device error)
+#define ST_OFFSETS 0x20u        // offsets[n_reads] != n_bytes
+#define ST_POOL 0x40u           // a bin needed a bigger table than the pool holds
+
+namespace gerbil {
+
+// 32 bases starting at global base position pos (pos >= -32).
+__device__ __forceinline__ uint64_t window32(const uint64_t* __restrict__ P, int64_t pos) {
+    int64_t q = pos >> 5;  // floor division (arithmetic shift)
+    uint32_t r = (uint32_t)(pos & 31);
+    uint64_t a = P[q];
+    if (r == 0) return a;
+    uint64_t b = P[q + 1];
+    return (a << (2 * r)) | (b >> (64 - 2 * r));
+}
+
+// Reverse complement of 32 packed bases: reverse the order of the 2-bit
+// groups and complement each (A<->T is 00<->11, C<->G is 01<->10: bitwise NOT).
+__device__ __forceinline__ uint64_t revcomp32(uint64_t x) {
+    x = __builtin_bitreverse64(~x);
+    // bit reversal also swapped the two bits inside each group; swap back
+    return ((x >> 1) & 0x5555555555555555ull) | ((x & 0x5555555555555555ull) << 1);
+}
+
+// Forward and reverse-complement keys of the k-mer at position p.
+template <int W>
+__device__ __forceinline__ void extract_kmer(const uint64_t* __restrict__ P, int64_t p, uint32_t k,
+                                             uint64_t (&fw)[W], uint64_t (&rc)[W]) {
+    const uint32_t r = k - 32u * (W - 1);  // bases in the last word, 1..32
+    const uint32_t sh = 2u * (32u - r);
+#pragma unroll
+    for (int i = 0; i < W - 1; i++) {
+        fw[i] = window32(P, p + 32 * i);
+        rc[i] = revcomp32(window32(P, p + (int64_t)k - 32 * (i + 1)));
+    }
+    uint64_t tail = window32(P, p + 32 * (W - 1));
+    fw[W - 1] = sh ? (tail >> sh) : tail;
+    uint64_t rtail = revcomp32(window32(P, p - 32 + (int64_t)r));
+    rc[W - 1] = sh ? (rtail >> sh) : rtail;
+}
+
+// canonical = lexicographically smaller of fw and rc (compare from word 0).
+template <int W>
+__device__ __forceinline__ void canonical_of(const uint64_t (&fw)[W], const uint64_t (&rc)[W], uint64_t (&key)[W]) {
+    bool take_rc = false, decided = false;
+#pragma unroll
+    for (int i = 0; i < W; i++) {
+        if (!decided && fw[i] != rc[i]) {
+            take_rc = rc[i] < fw[i];
+            decided = true;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < W; i++) key[i] = take_rc ? rc[i] : fw[i];
+}
+
+// Avalanche step of MurmurHash3 (fmix64).
+__device__ __forceinline__ uint64_t fmix64(uint64_t z) {
+    z ^= z >> 33;
+    z *= 0xff51afd7ed558ccdull;
+    z ^= z >> 33;
+    z *= 0xc4ceb9fe1a85ec53ull;
+    z ^= z >> 33;
+    return z;
+}
+
+// Hash of a key: multiplicative combine of the words, then an avalanche.
+// Only slot positions depend on it, never results.
+template <int W>
+__device__ __forceinline__ uint64_t key_hash(const uint64_t (&key)[W], uint64_t seed) {
+    uint64_t h = seed;
+#pragma unroll
+    for (int i = 0; i < W; i++) h = (h ^ key[i]) * 0x9E3779B97F4A7C15ull;
+    return fmix64(h);
+}
+
+// Map a 32-bit value uniformly onto [0, n) (multiply-shift range reduction).
+__device__ __forceinline__ uint32_t fastrange32(uint32_t x, uint32_t n) {
+    return (uint32_t)(((uint64_t)x * (uint64_t)n) >> 32);
+}
+
+// Agent-scope (device-coherent) accessors for memory shared between
+// workgroups. They compile to loads/stores/atomics with the sc1 bit on gfx950,
+// which bypass the non-coherent per-CU cache.
+template <typename T>
+__device__ __forceinline__ T ld_dev(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T, typename U>
+__device__ __forceinline__ void st_dev(T* p, U v) {
+    __hip_atomic_store(p, static_cast<T>(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T, typename U>
+__device__ __forceinline__ T add_dev(T* p, U v) {
+    return __hip_atomic_fetch_add(p, static_cast<T>(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T, typename U, typename V>
+__device__ __forceinline__ T cas_dev(T* p, U expected_in, V desired) {
+    T expected = static_cast<T>(expected_in);
+    __hip_atomic_compare_exchange_strong(p, &expected, static_cast<T>(desired), __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    return expected;  // the value found (== old expected on success)
+}
+__device__ __forceinline__ void set_status(uint32_t* status, uint32_t bits) {
+    __hip_atomic_fetch_or(status, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wave-aggregated reservation of `want` (0 or 1 per lane) slots on a global
+// cursor: one atomic per wave; returns this lane's index.
+__device__ __forceinline__ uint64_t wave_reserve(uint64_t* cursor, bool want) {
+    uint64_t mask = __ballot(want);
+    if (mask == 0) return 0;
+    uint32_t lane = __lane_id();
+    uint32_t leader = __ffsll((unsigned long long)mask) - 1;
+    uint32_t rank = __popcll(mask & ((1ull << lane) - 1ull));
+    uint64_t base = 0;
+    if (lane == leader) base = add_dev(cursor, (uint64_t)__popcll(mask));
+    base = __shfl(base, leader);
+    return base + rank;
+}
+
+}  // namespace gerbil

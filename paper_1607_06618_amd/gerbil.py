@@ -1,0 +1,323 @@
+"""ctypes binding of libgerbil.so (the C ABI in include/gerbil.h).
+
+Every function here marshals arguments and calls the library; all steps of
+the counting path run in the HIP kernels behind the C ABI. PyTorch supplies
+device memory and streams only. If the shared library is missing the import
+of the library fails loudly: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgerbil.so")
+
+GERBIL_OK = 0
+GERBIL_EINVAL = -1
+GERBIL_EUNSUPPORTED = -2
+GERBIL_ECAPACITY = -3
+GERBIL_EDEVICE = -4
+
+GERBIL_PLAIN = 0
+GERBIL_BATCHED = 1
+GERBIL_ORDER_KMC2 = 0
+GERBIL_ORDER_LEX = 1
+GERBIL_TABLE_AUTO = 0
+GERBIL_TABLE_HBM = 1
+GERBIL_TABLE_LDS = 2
+
+# device status bits (see gerbil_report.status)
+ST_OUT_CAP = 0x1
+ST_OVF_CAP = 0x2
+ST_SUPERM_CAP = 0x4
+ST_COUNT_SAT = 0x8
+ST_SPIN = 0x10
+ST_OFFSETS = 0x20
+ST_POOL = 0x40
+
+u32, u64, f32, vp = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_float, ctypes.c_void_p
+
+
+class gerbil_params(ctypes.Structure):
+    _fields_ = [("k", u32), ("m", u32), ("n_bins", u32), ("threshold", u32), ("canonical", u32),
+                ("order", u32), ("bin_map", vp), ("mode", u32), ("table", u32), ("load_factor", f32),
+                ("max_probes", u32), ("block", u32), ("pool", u32), ("overflow_cap", u64),
+                ("superm_cap", u64), ("table_budget", u64)]
+
+
+class gerbil_encoded(ctypes.Structure):
+    _fields_ = [("n_reads", u64), ("n_bytes", u64), ("k", u32), ("reserved", u32), ("n_words", u64),
+                ("n_mask", u64), ("packed", vp), ("valid", vp), ("read_start", vp), ("kmer_ok", vp),
+                ("n_valid", vp), ("status", vp)]
+
+
+class gerbil_bins(ctypes.Structure):
+    _fields_ = [("k", u32), ("m", u32), ("n_bins", u32), ("tile", u32), ("cap_superm", u64), ("n_bytes", u64),
+                ("packed", vp), ("desc", vp), ("bin_off", vp), ("bin_kmers", vp), ("n_superm", vp),
+                ("status", vp)]
+
+
+class gerbil_counted(ctypes.Structure):
+    _fields_ = [("k", u32), ("W", u32), ("threshold", u32), ("hist_len", u32), ("cap", u64),
+                ("overflow_cap", u64), ("n_out", vp), ("hist", vp), ("n_overflow", vp), ("max_count", vp),
+                ("status", vp), ("n_superm", vp), ("bin_status", vp)]
+
+
+class gerbil_report(ctypes.Structure):
+    _fields_ = [("n_valid", u64), ("n_superm", u64), ("n_out", u64), ("n_overflow", u64), ("max_count", u64),
+                ("status", u32), ("reserved", u32)]
+
+
+class GerbilError(RuntimeError):
+    def __init__(self, fn: str, status: int, report: Optional[gerbil_report] = None):
+        self.status = status
+        self.report = report
+        msg = f"{fn} failed: {status_string(status)} ({status})"
+        if report is not None:
+            msg += (f"; device status 0x{report.status:x}, n_out={report.n_out}, n_superm={report.n_superm}, "
+                    f"n_overflow={report.n_overflow}")
+        super().__init__(msg)
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libgerbil.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} is missing: build the HIP library first "
+                                f"(python -m paper_1607_06618_amd.build)")
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    lib.gerbil_version.restype = u32
+    lib.gerbil_version.argtypes = []
+    lib.gerbil_status_string.restype = ctypes.c_char_p
+    lib.gerbil_status_string.argtypes = [ctypes.c_int32]
+    lib.gerbil_encode_workspace.argtypes = [u64, u64, u32, P(u64)]
+    lib.gerbil_encode.argtypes = [vp, vp, u64, u64, u32, vp, u64, P(gerbil_encoded), vp]
+    lib.gerbil_bin_workspace.argtypes = [P(gerbil_encoded), P(gerbil_params), P(u64)]
+    lib.gerbil_bin.argtypes = [P(gerbil_encoded), P(gerbil_params), vp, u64, P(gerbil_bins), vp]
+    lib.gerbil_count_workspace.argtypes = [P(gerbil_bins), P(gerbil_params), P(u64)]
+    lib.gerbil_count.argtypes = [P(gerbil_bins), P(gerbil_params), vp, u64, vp, vp, u64, P(gerbil_counted), vp]
+    lib.gerbil_histogram.argtypes = [P(gerbil_counted), vp, u32, vp]
+    lib.gerbil_result.argtypes = [P(gerbil_encoded), P(gerbil_bins), P(gerbil_counted), P(gerbil_report), vp]
+    for name in ("gerbil_encode_workspace", "gerbil_encode", "gerbil_bin_workspace", "gerbil_bin",
+                 "gerbil_count_workspace", "gerbil_count", "gerbil_histogram", "gerbil_result"):
+        getattr(lib, name).restype = ctypes.c_int32
+    _lib = lib
+    return lib
+
+
+# ------------------------------------------------------------ C-ABI names
+
+def gerbil_version() -> int:
+    return int(load().gerbil_version())
+
+
+def status_string(status: int) -> str:
+    return load().gerbil_status_string(status).decode()
+
+
+gerbil_status_string = status_string
+
+
+def gerbil_encode_workspace(n_reads: int, n_bytes: int, k: int) -> int:
+    out = u64(0)
+    st = load().gerbil_encode_workspace(n_reads, n_bytes, k, ctypes.byref(out))
+    if st:
+        raise GerbilError("gerbil_encode_workspace", st)
+    return out.value
+
+
+def gerbil_encode(ascii_ptr: int, offsets_ptr: int, n_reads: int, n_bytes: int, k: int, ws_ptr: int,
+                  ws_bytes: int, out: gerbil_encoded, stream: int = 0) -> int:
+    return load().gerbil_encode(ascii_ptr, offsets_ptr, n_reads, n_bytes, k, ws_ptr, ws_bytes, ctypes.byref(out),
+                                stream)
+
+
+def gerbil_bin_workspace(enc: gerbil_encoded, p: gerbil_params) -> int:
+    out = u64(0)
+    st = load().gerbil_bin_workspace(ctypes.byref(enc), ctypes.byref(p), ctypes.byref(out))
+    if st:
+        raise GerbilError("gerbil_bin_workspace", st)
+    return out.value
+
+
+def gerbil_bin(enc: gerbil_encoded, p: gerbil_params, ws_ptr: int, ws_bytes: int, out: gerbil_bins,
+               stream: int = 0) -> int:
+    return load().gerbil_bin(ctypes.byref(enc), ctypes.byref(p), ws_ptr, ws_bytes, ctypes.byref(out), stream)
+
+
+def gerbil_count_workspace(bins: gerbil_bins, p: gerbil_params) -> int:
+    out = u64(0)
+    st = load().gerbil_count_workspace(ctypes.byref(bins), ctypes.byref(p), ctypes.byref(out))
+    if st:
+        raise GerbilError("gerbil_count_workspace", st)
+    return out.value
+
+
+def gerbil_count(bins: gerbil_bins, p: gerbil_params, ws_ptr: int, ws_bytes: int, keys_ptr: int, counts_ptr: int,
+                 cap: int, state: gerbil_counted, stream: int = 0) -> int:
+    return load().gerbil_count(ctypes.byref(bins), ctypes.byref(p), ws_ptr, ws_bytes, keys_ptr, counts_ptr, cap,
+                               ctypes.byref(state), stream)
+
+
+def gerbil_histogram(state: gerbil_counted, hist_ptr: int, length: int, stream: int = 0) -> int:
+    return load().gerbil_histogram(ctypes.byref(state), hist_ptr, length, stream)
+
+
+def gerbil_result(enc: Optional[gerbil_encoded], bins: Optional[gerbil_bins], state: Optional[gerbil_counted],
+                  stream: int = 0):
+    rep = gerbil_report()
+    st = load().gerbil_result(ctypes.byref(enc) if enc is not None else None,
+                              ctypes.byref(bins) if bins is not None else None,
+                              ctypes.byref(state) if state is not None else None, ctypes.byref(rep), stream)
+    return st, rep
+
+
+def check(fn: str, status: int):
+    if status != GERBIL_OK:
+        raise GerbilError(fn, status)
+
+
+# ------------------------------------------------------- torch-side driver
+
+def words(k: int) -> int:
+    return (k + 31) // 32
+
+
+def make_params(k: int, m: int, n_bins: int, threshold: int, mode: int = GERBIL_PLAIN, order: int = 0,
+                bin_map_ptr: int = 0, load_factor: float = 0.0, max_probes: int = 0, block: int = 0,
+                table: int = GERBIL_TABLE_AUTO, pool: int = 0, overflow_cap: int = 0, superm_cap: int = 0,
+                table_budget: int = 0) -> gerbil_params:
+    return gerbil_params(k=k, m=m, n_bins=n_bins, threshold=threshold, canonical=1, order=order,
+                         bin_map=bin_map_ptr or None, mode=mode, table=table, load_factor=load_factor,
+                         max_probes=max_probes, block=block, pool=pool, overflow_cap=overflow_cap,
+                         superm_cap=superm_cap, table_budget=table_budget)
+
+
+@dataclass
+class CountResult:
+    keys: np.ndarray      # uint64 [n, W], unspecified order
+    counts: np.ndarray    # uint32 [n]
+    hist: np.ndarray      # uint64 [hist_len]
+    report: gerbil_report
+
+    def sorted(self):
+        """Pairs sorted by key (for comparisons)."""
+        if self.keys.shape[0] == 0:
+            return self.keys, self.counts
+        order = np.lexsort(self.keys.T[::-1])
+        return self.keys[order], self.counts[order]
+
+
+def _stream_handle(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+class Job:
+    """Device buffers and C-ABI state of one counting run (encode -> bin -> count -> histogram).
+
+    Workspaces are torch tensors on the current device; the library itself
+    never allocates. ``run`` enqueues the whole path on ``stream``.
+    """
+
+    def __init__(self, ascii_d, offsets_d, n_bytes: int, params: gerbil_params, hist_len: int = 256,
+                 cap: Optional[int] = None, stream=None):
+        import torch
+        self.torch = torch
+        self.ascii_d, self.offsets_d = ascii_d, offsets_d
+        self.n_reads = offsets_d.numel() - 1
+        self.n_bytes = n_bytes
+        self.p = params
+        self.hist_len = hist_len
+        self.W = words(params.k)
+        self.stream = stream
+        dev = ascii_d.device
+        self.enc = gerbil_encoded()
+        self.bins = gerbil_bins()
+        self.state = gerbil_counted()
+        self.ws_enc = torch.empty(gerbil_encode_workspace(self.n_reads, n_bytes, params.k), dtype=torch.uint8,
+                                  device=dev)
+        self.cap = cap
+        self.ws_bin = None
+        self.ws_count = None
+        self.keys_d = None
+        self.counts_d = None
+        self.hist_d = torch.zeros(hist_len, dtype=torch.int64, device=dev)
+
+    def encode(self):
+        s = _stream_handle(self.stream)
+        check("gerbil_encode", gerbil_encode(self.ascii_d.data_ptr(), self.offsets_d.data_ptr(), self.n_reads,
+                                             self.n_bytes, self.p.k, self.ws_enc.data_ptr(), self.ws_enc.numel(),
+                                             self.enc, s))
+
+    def bin(self):
+        torch = self.torch
+        s = _stream_handle(self.stream)
+        if self.ws_bin is None:
+            self.ws_bin = torch.empty(gerbil_bin_workspace(self.enc, self.p), dtype=torch.uint8,
+                                      device=self.ascii_d.device)
+        check("gerbil_bin", gerbil_bin(self.enc, self.p, self.ws_bin.data_ptr(), self.ws_bin.numel(), self.bins, s))
+
+    def prepare_count(self, n_valid: Optional[int] = None):
+        """Size the count workspace and output arrays (synchronises once)."""
+        torch = self.torch
+        if self.ws_count is None:
+            self.ws_count = torch.empty(gerbil_count_workspace(self.bins, self.p), dtype=torch.uint8,
+                                        device=self.ascii_d.device)
+        if self.keys_d is None:
+            if self.cap is None:
+                if n_valid is None:
+                    st, rep = gerbil_result(self.enc, None, None, _stream_handle(self.stream))
+                    n_valid = rep.n_valid
+                self.cap = max(1, n_valid // max(1, self.p.threshold) + 1)
+            self.keys_d = torch.empty(self.cap * self.W, dtype=torch.int64, device=self.ascii_d.device)
+            self.counts_d = torch.empty(self.cap, dtype=torch.int32, device=self.ascii_d.device)
+
+    def count(self):
+        s = _stream_handle(self.stream)
+        check("gerbil_count", gerbil_count(self.bins, self.p, self.ws_count.data_ptr(), self.ws_count.numel(),
+                                           self.keys_d.data_ptr(), self.counts_d.data_ptr(), self.cap, self.state, s))
+        check("gerbil_histogram", gerbil_histogram(self.state, self.hist_d.data_ptr(), self.hist_len, s))
+
+    def run(self):
+        """Enqueue encode -> bin -> count -> histogram (sizes taken on the first call)."""
+        self.encode()
+        self.bin()
+        if self.ws_count is None or self.keys_d is None:
+            self.prepare_count()
+        self.count()
+
+    def result(self, raise_on_error: bool = True) -> CountResult:
+        st, rep = gerbil_result(self.enc, self.bins, self.state, _stream_handle(self.stream))
+        if st != GERBIL_OK and raise_on_error:
+            raise GerbilError("gerbil_result", st, rep)
+        n = min(rep.n_out, self.cap or 0)
+        keys = self.keys_d[: n * self.W].cpu().numpy().view(np.uint64).reshape(n, self.W)
+        counts = self.counts_d[:n].cpu().numpy().view(np.uint32)
+        hist = self.hist_d.cpu().numpy().view(np.uint64)
+        return CountResult(keys, counts, hist, rep)
+
+
+def count_kmers(ascii: np.ndarray, offsets: np.ndarray, k: int, m: int, n_bins: int, threshold: int,
+                hist_len: int = 256, device: str = "cuda", **kw) -> CountResult:
+    """Convenience: copy host reads to the device and run the whole path once."""
+    import torch
+    a = torch.from_numpy(np.ascontiguousarray(ascii, dtype=np.uint8)).to(device)
+    o = torch.from_numpy(np.ascontiguousarray(offsets, dtype=np.uint64).view(np.int64)).to(device)
+    p = make_params(k, m, n_bins, threshold, **kw)
+    job = Job(a, o, int(offsets[-1]), p, hist_len=hist_len)
+    job.run()
+    return job.result()

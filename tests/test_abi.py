@@ -1,0 +1,92 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared
+symbol, validates arguments before any launch, and the Python structs match
+the C layout."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from conftest import ROOT
+from paper_1607_06618_amd import gerbil as g
+
+HEADER = os.path.join(ROOT, "include", "gerbil.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const char\*|uint32_t|int32_t)\s+(gerbil_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = g.load()
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", g.LIB_PATH], capture_output=True, text=True, check=True)
+    exported = set(re.findall(r" T (gerbil_\w+)", out.stdout))
+    assert set(names) <= exported
+    # nothing else with the gerbil_ prefix leaks out
+    assert exported == set(names)
+
+
+def test_version_and_status_strings():
+    assert g.gerbil_version() == 0x000100
+    assert g.status_string(g.GERBIL_OK) == "ok"
+    assert "capacity" in g.status_string(g.GERBIL_ECAPACITY)
+
+
+def test_encode_workspace_validation():
+    assert g.gerbil_encode_workspace(10, 1000, 32) > 1000 // 4
+    with pytest.raises(g.GerbilError):
+        g.gerbil_encode_workspace(10, 1000, 1)
+    with pytest.raises(g.GerbilError):
+        g.gerbil_encode_workspace(10, 1000, 257)
+
+
+def test_param_validation_before_launch():
+    enc = g.gerbil_encoded(n_reads=1, n_bytes=100, k=32)
+    good = g.make_params(32, 7, 64, 2)
+    assert g.gerbil_bin_workspace(enc, good) > 0
+    for bad in (g.make_params(32, 32, 64, 2), g.make_params(32, 0, 64, 2), g.make_params(32, 16, 64, 2),
+                g.make_params(32, 7, 0, 2), g.make_params(32, 7, 5000, 2), g.make_params(32, 7, 64, 0),
+                g.make_params(32, 7, 64, 2, block=100), g.make_params(32, 7, 64, 2, load_factor=0.99)):
+        with pytest.raises(g.GerbilError) as e:
+            g.gerbil_bin_workspace(enc, bad)
+        assert e.value.status == g.GERBIL_EINVAL
+    p = g.make_params(32, 7, 64, 2)
+    p.canonical = 0
+    with pytest.raises(g.GerbilError) as e:
+        g.gerbil_bin_workspace(enc, p)
+    assert e.value.status == g.GERBIL_EUNSUPPORTED
+    # k must match the encoding
+    with pytest.raises(g.GerbilError):
+        g.gerbil_bin_workspace(enc, g.make_params(33, 7, 64, 2))
+    # null workspace / output pointers are rejected without touching the device
+    assert g.gerbil_encode(0, 0, 1, 100, 32, 0, 0, g.gerbil_encoded()) == g.GERBIL_EINVAL
+
+
+def test_struct_layout_matches_header(tmp_path):
+    structs = {
+        "gerbil_params": g.gerbil_params, "gerbil_encoded": g.gerbil_encoded, "gerbil_bins": g.gerbil_bins,
+        "gerbil_counted": g.gerbil_counted, "gerbil_report": g.gerbil_report,
+    }
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gerbil.h"', "int main(void) {"]
+    for sname, cls in structs.items():
+        lines.append(f'  printf("{sname} %zu\\n", sizeof({sname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{sname}.{fname} %zu\\n", offsetof({sname}, {fname}));')
+    lines.append("  return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"), "-I", "/opt/rocm/include",
+                    str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = dict(ln.split() for ln in out if ln)
+    for sname, cls in structs.items():
+        assert int(got[sname]) == ctypes.sizeof(cls), sname
+        for fname, _ in cls._fields_:
+            assert int(got[f"{sname}.{fname}"]) == getattr(cls, fname).offset, (sname, fname)
