@@ -1,0 +1,256 @@
+#!/usr/bin/env python3
+"""Benchmark of the counting path on one MI355X.
+
+A step is one pass of the whole path over the workload's reads, already
+resident in HBM: encode -> bin -> count -> histogram. The headline is the
+BATCHED schedule (all bins in one persistent launch); the PLAIN schedule (one
+launch sequence per bin) is timed beside it on the same inputs. The unit of
+work is a valid (N-free) k-mer window.
+
+Prints ONE JSON line (see the design doc for every field).
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "canonical k-mers counted/s at k=65 (batched vs per-bin); HBM GB/s; p50/p99"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse_args(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c2_k65")
+    ap.add_argument("--scale", type=float, default=1.0, help="genome scale factor (1.0 = the named workload)")
+    ap.add_argument("--modes", default="batched,plain")
+    ap.add_argument("--pool", type=int, default=0)
+    ap.add_argument("--load", type=float, default=0.0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU-oracle sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args(argv)
+
+
+class HipEvents:
+    """hipEvent_t pairs through the HIP runtime (the library records them on its stream)."""
+
+    def __init__(self):
+        self.hip = ctypes.CDLL("libamdhip64.so")
+        self.hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+        self.hip.hipEventSynchronize.argtypes = [ctypes.c_void_p]
+        self.hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+
+    def pair(self):
+        arr = (ctypes.c_void_p * 2)()
+        for i in range(2):
+            ev = ctypes.c_void_p()
+            rc = self.hip.hipEventCreate(ctypes.byref(ev))
+            if rc != 0:
+                raise RuntimeError(f"hipEventCreate failed ({rc})")
+            arr[i] = ev
+        return arr
+
+    def elapsed_ms(self, arr) -> float:
+        self.hip.hipEventSynchronize(arr[1])
+        ms = ctypes.c_float()
+        rc = self.hip.hipEventElapsedTime(ctypes.byref(ms), arr[0], arr[1])
+        if rc != 0:
+            raise RuntimeError(f"hipEventElapsedTime failed ({rc})")
+        return float(ms.value)
+
+
+def percentile(xs, q):
+    s = sorted(xs)
+    if not s:
+        return None
+    i = min(len(s) - 1, max(0, int(math.ceil(q / 100.0 * len(s))) - 1))
+    return s[i]
+
+
+def cpu_baseline(ascii_, offsets, k, threshold, target_s):
+    """The oracle as it stands, single-threaded, on a leading sample of reads."""
+    import numpy as np
+
+    import oracle
+    n_reads = offsets.size - 1
+    # calibrate on a small sample, then size the timed sample to ~target_s
+    n0 = min(n_reads, 2000)
+    t = time.perf_counter()
+    r0 = oracle.count(ascii_, offsets[: n0 + 1], k, threshold=threshold)
+    dt0 = max(1e-3, time.perf_counter() - t)
+    per_window = dt0 / max(1, r0.n_valid)
+    want_windows = target_s / per_window
+    avg_windows = max(1.0, r0.n_valid / n0)
+    n = int(min(n_reads, max(n0, want_windows / avg_windows)))
+    t = time.perf_counter()
+    r = oracle.count(ascii_, offsets[: n + 1], k, threshold=threshold)
+    dt = time.perf_counter() - t
+    return {"value": r.n_valid / dt, "unit": "k-mers/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n} of {n_reads} reads ({r.n_valid} valid windows), {dt:.1f} s single-threaded "
+                      f"sort-and-count"}
+
+
+def main(argv=None):
+    args = parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU sharding is a design note only)", file=sys.stderr, flush=True)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1607_06618_amd import gerbil as g
+
+    g.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = synth.CONFIGS[args.config]
+    if args.scale != 1.0:
+        w = w.scaled(args.scale)
+    t0 = time.perf_counter()
+    ascii_, offsets = w.generate(threads=16)
+    gen_s = time.perf_counter() - t0
+    print(f"[bench] generated {w.name}: {ascii_.size / 1e9:.2f} GB ASCII, {offsets.size - 1} reads in {gen_s:.1f} s",
+          file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ascii_d = torch.from_numpy(ascii_).to(dev)
+    offsets_d = torch.from_numpy(offsets.view(np.int64)).to(dev)
+    torch.cuda.synchronize()
+    bin_map_d = None
+    if w.skew_bins:
+        bin_map_d = torch.from_numpy(synth_bin_map(w).view(np.int32)).to(dev)
+
+    evs = HipEvents()
+    modes = [m.strip() for m in args.modes.split(",") if m.strip()]
+    results = {}
+    shared_out = {}
+    for mode_name in modes:
+        mode = g.GERBIL_BATCHED if mode_name == "batched" else g.GERBIL_PLAIN
+        ev = evs.pair()
+        p = g.make_params(w.k, w.m, w.n_bins, w.threshold, mode=mode, pool=args.pool, load_factor=args.load,
+                          bin_map_ptr=bin_map_d.data_ptr() if bin_map_d is not None else 0,
+                          timing_events=ctypes.addressof(ev))
+        job = g.Job(ascii_d, offsets_d, int(offsets[-1]), p, hist_len=65536)
+        # first pass sizes the workspaces (synchronises); outputs are shared between schedules
+        job.encode()
+        job.bin()
+        st, rep = g.gerbil_result(job.enc, job.bins, None)
+        if "keys" in shared_out:
+            job.cap, job.keys_d, job.counts_d = shared_out["cap"], shared_out["keys"], shared_out["counts"]
+        job.prepare_count(n_valid=rep.n_valid)
+        shared_out.update(cap=job.cap, keys=job.keys_d, counts=job.counts_d)
+        for _ in range(args.warmup):
+            job.run()
+        res = job.result()
+        torch.cuda.synchronize()
+        step_ms = []
+        starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        kev = [evs.pair() for _ in range(args.steps)]   # counting-kernel events, one pair per step
+        torch.cuda.synchronize()
+        wall0 = time.perf_counter()
+        starts[0].record()
+        for s in range(args.steps):
+            job.p.timing_events = ctypes.cast(kev[s], ctypes.c_void_p)
+            job.run()
+            starts[s + 1].record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - wall0
+        for s in range(args.steps):
+            step_ms.append(starts[s].elapsed_time(starts[s + 1]))
+        kms_all = [evs.elapsed_ms(e) for e in kev]
+        kms = sum(kms_all) / len(kms_all)
+        res_t = job.result()
+        results[mode_name] = dict(job=job, res=res_t, wall=wall, step_ms=step_ms, kernel_ms=kms, ev=ev)
+        print(f"[bench] {mode_name}: {args.steps} steps in {wall:.3f} s, step p50 {percentile(step_ms, 50):.2f} ms, "
+              f"counting kernel {kms:.2f} ms", file=sys.stderr, flush=True)
+
+    head = "batched" if "batched" in results else modes[0]
+    R = results[head]
+    rep = R["res"].report
+    n_valid = rep.n_valid
+    value = n_valid * args.steps / R["wall"]
+    ms_per_step = 1000.0 * R["wall"] / args.steps
+    hist = R["res"].hist.astype(np.float64)
+    n_distinct = int(hist[1:].sum())
+    c = np.arange(hist.size, dtype=np.float64)
+    checks = {"sum_c_h_equals_valid": bool(rep.max_count < hist.size - 1 and int((c * hist).sum()) == n_valid)}
+    if len(results) > 1:
+        other = [m for m in results if m != head][0]
+        o = results[other]["res"]
+        checks["modes_agree"] = bool(o.report.n_out == rep.n_out and np.array_equal(o.hist, R["res"].hist))
+
+    # algorithmic bytes of the persistent counting kernel per launch
+    W = (w.k + 31) // 32
+    E = 8 * W + 4
+    packed_bytes = 0.25 * (n_valid + rep.n_superm * (w.k - 1))
+    alg_bytes = (8.0 * rep.n_superm + packed_bytes + n_distinct * (2 * E + 12) + (n_valid - n_distinct) * 8.0
+                 + rep.n_out * E)
+    achieved = alg_bytes / (R["kernel_ms"] / 1000.0) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_count_persistent" if head == "batched" else "k_count_bin+k_compact",
+                "kernel_ms": round(R["kernel_ms"], 3), "alg_bytes": int(alg_bytes)}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(ascii_, offsets, w.k, w.threshold, args.cpu_seconds)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "k-mers/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": w.name, "description": w.note, "k": w.k, "m": w.m, "n_bins": w.n_bins,
+                   "threshold": w.threshold, "reads": int(offsets.size - 1), "bytes": int(ascii_.size),
+                   "valid_windows": int(n_valid), "super_mers": int(rep.n_superm), "distinct": n_distinct,
+                   "pairs_out": int(rep.n_out), "schedule": head},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "p50_ms": percentile(R["step_ms"], 50), "p99_ms": percentile(R["step_ms"], 99),
+        "checks": checks,
+    }
+    for m, r in results.items():
+        out[f"{m}_kmers_per_s"] = n_valid * args.steps / r["wall"]
+        out[f"{m}_ms_per_step"] = 1000.0 * r["wall"] / args.steps
+        out[f"{m}_count_kernel_ms"] = r["kernel_ms"]
+    if "batched" in results and "plain" in results:
+        out["batched_over_plain"] = results["plain"]["wall"] / results["batched"]["wall"]
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def synth_bin_map(w):
+    """Seeded minimizer -> bin map with log-normal bin weights (skewed bins)."""
+    import numpy as np
+    import synth as s
+    m, nb = w.m, w.n_bins
+    rng = np.random.default_rng(w.seed)
+    weights = np.exp(rng.normal(0.0, 0.97, nb))
+    codes = np.arange(4 ** m)
+    order = rng.permutation(codes)
+    # assign m-mers round-robin weighted by the bin weights
+    share = weights / weights.sum()
+    bounds = np.floor(np.cumsum(share) * codes.size).astype(np.int64)
+    bmap = np.searchsorted(bounds, np.arange(codes.size), side="right").clip(0, nb - 1)
+    out = np.empty(codes.size, dtype=np.uint32)
+    out[order] = bmap.astype(np.uint32)
+    del s
+    return out
+
+
+if __name__ == "__main__":
+    sys.exit(main())

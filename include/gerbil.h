@@ -96,6 +96,9 @@ typedef struct {
     uint64_t overflow_cap;   /* emergency-area capacity in keys; 0 = default                     */
     uint64_t superm_cap;     /* super-mer descriptor capacity; 0 = default estimate              */
     uint64_t table_budget;   /* bytes of workspace for hash tables; 0 = default                  */
+    hipEvent_t* timing_events; /* optional hipEvent_t[2] recorded on the stream just before and just
+                                  after the main counting kernel(s): the persistent kernel (BATCHED)
+                                  or the per-bin insert and dump launches (PLAIN); NULL = none      */
 } gerbil_params;
 
 /* Output of gerbil_encode. All pointers point into the encode workspace. */

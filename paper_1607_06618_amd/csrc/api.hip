@@ -128,19 +128,17 @@ int32_t check_params(const gerbil_params* p) {
 }
 
 // ----------------------------------------------------------------- count
+constexpr uint32_t kDefaultPool = 4;
+constexpr uint32_t kCmpChunk = 4096;   // slots per dump item of the batched schedule
+
 struct CountLayout {
     uint64_t* scalars;   // [0] n_out [1] n_ovf [2] max_count [3] status
     uint64_t* hist;
     uint64_t* ovf_keys;
-    uint64_t* tables;
-};
-
-struct CountSizing {
-    uint32_t W;
-    uint64_t slots;        // per table
-    uint64_t table_bytes;  // per table
-    uint32_t pool;
-    uint64_t ovf_cap;      // power of two
+    // batched plan
+    uint32_t *order, *nb, *n_ins, *n_cmp, *ins_done, *cmp_done, *seg_code;
+    uint64_t *seg_start, *cursor;
+    uint8_t* pool;
 };
 
 uint64_t slots_for(uint64_t kmers, float load) {
@@ -151,51 +149,37 @@ uint64_t slots_for(uint64_t kmers, float load) {
     return nb * kBucket;
 }
 
-uint64_t table_bytes(uint64_t slots, uint32_t W) {
-    return align_up(slots * 8) + align_up(slots * 8 * (W - 1)) + align_up(slots * 4);
-}
-
-Table table_at(uint64_t* base, uint64_t slots, uint32_t W) {
-    uint8_t* p = (uint8_t*)base;
-    Table t;
-    t.stride = slots;
-    t.w0 = (uint64_t*)p;
-    p += align_up(slots * 8);
-    t.rest = (uint64_t*)p;
-    p += align_up(slots * 8 * (W - 1));
-    t.cnt = (uint32_t*)p;
-    return t;
-}
-
-uint64_t count_layout(const CountSizing& z, void* ws, CountLayout* L) {
+// Everything but the table pool.
+uint64_t count_fixed(uint32_t W, uint64_t ovf_cap, uint32_t n_bins, bool batched, void* ws, CountLayout* L) {
     Carve c(ws);
     CountLayout l;
+    memset(&l, 0, sizeof(l));
     l.scalars = c.take<uint64_t>(8);
     l.hist = c.take<uint64_t>(kHistInternal);
-    l.ovf_keys = c.take<uint64_t>(z.ovf_cap * z.W);
-    l.tables = (uint64_t*)c.take<uint8_t>(z.table_bytes * z.pool);
+    l.ovf_keys = c.take<uint64_t>(ovf_cap * W);
+    if (batched) {
+        l.order = c.take<uint32_t>(n_bins);
+        l.nb = c.take<uint32_t>(n_bins);
+        l.n_ins = c.take<uint32_t>(n_bins);
+        l.n_cmp = c.take<uint32_t>(n_bins);
+        l.ins_done = c.take<uint32_t>(n_bins);
+        l.cmp_done = c.take<uint32_t>(n_bins);
+        l.seg_code = c.take<uint32_t>(2 * n_bins);
+        l.seg_start = c.take<uint64_t>(2 * n_bins + 1);
+        l.cursor = c.take<uint64_t>(4);
+    }
+    l.pool = ws ? (uint8_t*)ws + c.used : nullptr;
     if (L) *L = l;
     return c.used;
 }
 
-int32_t count_sizing(const gerbil_bins* b, const gerbil_params* p, CountSizing* z) {
-    int32_t st = check_params(p);
-    if (st) return st;
-    if (!b || p->k != b->k || p->n_bins != b->n_bins) return GERBIL_EINVAL;
-    std::vector<uint64_t> kmers(b->n_bins);
-    if (hipDeviceSynchronize() != hipSuccess) return GERBIL_EDEVICE;
-    if (hipMemcpy(kmers.data(), b->bin_kmers, 8 * (size_t)b->n_bins, hipMemcpyDeviceToHost) != hipSuccess)
-        return GERBIL_EDEVICE;
-    uint64_t mx = 1;
-    for (uint64_t v : kmers) mx = std::max(mx, v);
-    float load = p->load_factor > 0 ? p->load_factor : kDefaultLoad;
-    z->W = words_for(p->k);
-    z->slots = slots_for(mx, load);
-    z->table_bytes = table_bytes(z->slots, z->W);
-    z->pool = 1;
-    z->ovf_cap = next_pow2(p->overflow_cap ? p->overflow_cap : kDefaultOverflow);
-    return GERBIL_OK;
+uint64_t ovf_capacity(const gerbil_params* p) { return next_pow2(p->overflow_cap ? p->overflow_cap : kDefaultOverflow); }
+uint32_t pool_size(const gerbil_params* p) {
+    if (p->mode != GERBIL_BATCHED) return 1;
+    uint32_t q = p->pool ? p->pool : kDefaultPool;
+    return std::min(q, p->n_bins);
 }
+float load_of(const gerbil_params* p) { return p->load_factor > 0 ? p->load_factor : kDefaultLoad; }
 
 int32_t hip_status(hipError_t e) { return e == hipSuccess ? GERBIL_OK : GERBIL_EDEVICE; }
 
@@ -333,11 +317,19 @@ int32_t gerbil_bin(const gerbil_encoded* enc, const gerbil_params* p, void* ws, 
 }
 
 int32_t gerbil_count_workspace(const gerbil_bins* bins, const gerbil_params* p, uint64_t* bytes) {
-    if (!bytes) return GERBIL_EINVAL;
-    CountSizing z;
-    int32_t st = count_sizing(bins, p, &z);
+    int32_t st = check_params(p);
     if (st) return st;
-    *bytes = count_layout(z, nullptr, nullptr);
+    if (!bytes || !bins || p->k != bins->k || p->n_bins != bins->n_bins) return GERBIL_EINVAL;
+    std::vector<uint64_t> kmers(bins->n_bins);
+    if (hipDeviceSynchronize() != hipSuccess) return GERBIL_EDEVICE;
+    if (hipMemcpy(kmers.data(), bins->bin_kmers, 8 * (size_t)bins->n_bins, hipMemcpyDeviceToHost) != hipSuccess)
+        return GERBIL_EDEVICE;
+    uint64_t mx = 1;
+    for (uint64_t v : kmers) mx = std::max(mx, v);
+    const uint32_t W = words_for(p->k);
+    const uint64_t slots = slots_for(mx, load_of(p));
+    *bytes = count_fixed(W, ovf_capacity(p), p->n_bins, p->mode == GERBIL_BATCHED, nullptr, nullptr) +
+             (uint64_t)pool_size(p) * pool_table_bytes(slots, W);
     return GERBIL_OK;
 }
 
@@ -348,30 +340,39 @@ int32_t gerbil_count(const gerbil_bins* bins, const gerbil_params* p, void* ws, 
     if (!bins || !ws || !state || (cap && (!keys || !counts))) return GERBIL_EINVAL;
     if (p->k != bins->k || p->n_bins != bins->n_bins) return GERBIL_EINVAL;
     if (((uintptr_t)ws) & (kAlign - 1)) return GERBIL_EINVAL;
-    if (p->mode == GERBIL_BATCHED) return GERBIL_EUNSUPPORTED;
     const uint32_t W = words_for(p->k);
     const uint32_t n_bins = bins->n_bins;
-
-    // The plain schedule reads the bin sizes once.
-    std::vector<uint64_t> off(n_bins + 1), kmers(n_bins);
-    uint64_t n_superm = 0;
-    hipError_t e = hipMemcpyAsync(off.data(), bins->bin_off, 8 * (size_t)(n_bins + 1), hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(kmers.data(), bins->bin_kmers, 8 * (size_t)n_bins, hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(&n_superm, bins->n_superm, 8, hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) return GERBIL_EDEVICE;
-
-    float load = p->load_factor > 0 ? p->load_factor : kDefaultLoad;
-    CountSizing z;
-    z.W = W;
-    uint64_t mx = 1;
-    for (uint64_t v : kmers) mx = std::max(mx, v);
-    z.slots = slots_for(mx, load);
-    z.table_bytes = table_bytes(z.slots, W);
-    z.pool = 1;
-    z.ovf_cap = next_pow2(p->overflow_cap ? p->overflow_cap : kDefaultOverflow);
+    const bool batched = p->mode == GERBIL_BATCHED;
+    const float load = load_of(p);
+    const uint64_t ovf_cap = ovf_capacity(p);
+    const uint32_t Q = pool_size(p);
     CountLayout L;
-    if (count_layout(z, ws, &L) > ws_bytes) return GERBIL_EINVAL;
+    const uint64_t fixed = count_fixed(W, ovf_cap, n_bins, batched, ws, &L);
+    if (fixed > ws_bytes) return GERBIL_EINVAL;
+    // The pool takes the rest of the workspace: Q tables of `slots` slots.
+    uint64_t slots = 0;
+    {
+        uint64_t per_table = (ws_bytes - fixed) / Q;
+        uint64_t s_guess = per_table / (8ull * W + 4);
+        while (s_guess >= kBucket && pool_table_bytes(s_guess, W) > per_table) s_guess -= s_guess / 64 + 1;
+        slots = s_guess - s_guess % kBucket;
+    }
+    if (slots < kBucket || slots / kBucket > 0xFFFFFFFFull) return GERBIL_EINVAL;
+
+    std::vector<uint64_t> off, kmers;
+    uint64_t n_superm = 0;
+    hipError_t e = hipSuccess;
+    if (!batched) {
+        // The plain schedule reads the bin sizes once.
+        off.resize(n_bins + 1);
+        kmers.resize(n_bins);
+        e = hipMemcpyAsync(off.data(), bins->bin_off, 8 * (size_t)(n_bins + 1), hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(kmers.data(), bins->bin_kmers, 8 * (size_t)n_bins, hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(&n_superm, bins->n_superm, 8, hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return GERBIL_EDEVICE;
+    }
 
     memset(state, 0, sizeof(*state));
     state->k = p->k;
@@ -379,7 +380,7 @@ int32_t gerbil_count(const gerbil_bins* bins, const gerbil_params* p, void* ws, 
     state->threshold = p->threshold;
     state->hist_len = kHistInternal;
     state->cap = cap;
-    state->overflow_cap = z.ovf_cap;
+    state->overflow_cap = ovf_cap;
     state->n_out = L.scalars;
     state->n_overflow = L.scalars + 1;
     state->max_count = L.scalars + 2;
@@ -398,7 +399,7 @@ int32_t gerbil_count(const gerbil_bins* bins, const gerbil_params* p, void* ws, 
     a.theta = p->max_probes ? p->max_probes : kDefaultTheta;
     a.seed = kHashSeed;
     a.ovf_keys = L.ovf_keys;
-    a.ovf_cap = z.ovf_cap;
+    a.ovf_cap = ovf_cap;
     a.n_ovf = state->n_overflow;
     a.out_keys = keys;
     a.out_counts = counts;
@@ -408,22 +409,58 @@ int32_t gerbil_count(const gerbil_bins* bins, const gerbil_params* p, void* ws, 
     a.max_count = state->max_count;
     a.status = state->status;
 
-    Table t = table_at(L.tables, z.slots, W);
     e = launch_fill_u64(L.scalars, 8, 0, stream);
     if (e == hipSuccess) e = launch_fill_u64(L.hist, kHistInternal, 0, stream);
-    if (e == hipSuccess) e = launch_fill_u64(t.w0, z.slots, GERBIL_EMPTY, stream);
-    if (e == hipSuccess) e = launch_fill_u32(t.cnt, z.slots, 0, stream);
+    for (uint32_t j = 0; j < Q && e == hipSuccess; j++) {
+        Table t = pool_table(L.pool, slots, W, j);
+        e = launch_fill_u64(t.w0, slots, GERBIL_EMPTY, stream);
+        if (e == hipSuccess) e = launch_fill_u32(t.cnt, slots, 0, stream);
+    }
     if (e != hipSuccess) return GERBIL_EDEVICE;
-    if (n_superm > bins->cap_superm) return GERBIL_OK;   // reported by gerbil_result as ECAPACITY
 
-    const uint32_t block = p->block ? p->block : kDefaultBlock;
-    for (uint32_t b = 0; b < n_bins && e == hipSuccess; b++) {
-        uint64_t d0 = off[b], d1 = off[b + 1];
-        if (d1 <= d0) continue;
-        uint64_t slots = std::min<uint64_t>(slots_for(kmers[b], load), z.slots);
-        uint32_t nb = (uint32_t)(slots / kBucket);
-        e = launch_count_bin(a, t, nb, d0, d1, block, stream);
-        if (e == hipSuccess) e = launch_compact(a, t, nb, stream);
+    if (batched) {
+        PersistArgs q;
+        q.pool = L.pool;
+        q.slots = slots;
+        q.Q = Q;
+        q.lag = Q / 2;
+        q.n_bins = n_bins;
+        q.ins_chunk = 256;
+        q.cmp_chunk = kCmpChunk;
+        q.load = load;
+        q.bin_off = bins->bin_off;
+        q.bin_kmers = bins->bin_kmers;
+        q.order = L.order;
+        q.nb = L.nb;
+        q.n_ins = L.n_ins;
+        q.n_cmp = L.n_cmp;
+        q.ins_done = L.ins_done;
+        q.cmp_done = L.cmp_done;
+        q.seg_code = L.seg_code;
+        q.seg_start = L.seg_start;
+        q.cursor = L.cursor;
+        q.n_superm = bins->n_superm;
+        q.superm_cap = bins->cap_superm;
+        q.status = state->status;
+        e = launch_plan(q, stream);
+        uint32_t grid = (uint32_t)device_cus() * persistent_blocks_per_cu(W, 256);
+        if (e == hipSuccess && p->timing_events) e = hipEventRecord(p->timing_events[0], stream);
+        if (e == hipSuccess) e = launch_count_persistent(a, q, grid, 256, stream);
+        if (e == hipSuccess && p->timing_events) e = hipEventRecord(p->timing_events[1], stream);
+    } else {
+        if (n_superm > bins->cap_superm) return GERBIL_OK;   // reported by gerbil_result as ECAPACITY
+        Table t = pool_table(L.pool, slots, W, 0);
+        const uint32_t block = p->block ? p->block : kDefaultBlock;
+        if (p->timing_events) e = hipEventRecord(p->timing_events[0], stream);
+        for (uint32_t b = 0; b < n_bins && e == hipSuccess; b++) {
+            uint64_t d0 = off[b], d1 = off[b + 1];
+            if (d1 <= d0) continue;
+            uint64_t want = std::min<uint64_t>(slots_for(kmers[b], load), slots);
+            uint32_t nb = (uint32_t)(want / kBucket);
+            e = launch_count_bin(a, t, nb, d0, d1, block, stream);
+            if (e == hipSuccess) e = launch_compact(a, t, nb, stream);
+        }
+        if (e == hipSuccess && p->timing_events) e = hipEventRecord(p->timing_events[1], stream);
     }
     if (e == hipSuccess) e = launch_overflow(a, stream);
     return hip_status(e);

@@ -68,6 +68,53 @@ struct CountArgs {
     uint32_t* status;
 };
 
+// Table j of a pool: [w0: slots][rest: (W-1) * slots][cnt: slots], each part 256-byte aligned.
+__host__ __device__ inline uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+__host__ __device__ inline uint64_t pool_table_bytes(uint64_t slots, uint32_t W) {
+    return align256(slots * 8) + align256(slots * 8 * (W - 1)) + align256(slots * 4);
+}
+__host__ __device__ inline Table pool_table(uint8_t* pool, uint64_t slots, uint32_t W, uint32_t j) {
+    uint8_t* p = pool + (uint64_t)j * pool_table_bytes(slots, W);
+    Table t;
+    t.stride = slots;
+    t.w0 = (uint64_t*)p;
+    p += align256(slots * 8);
+    t.rest = (uint64_t*)p;
+    p += align256(slots * 8 * (W - 1));
+    t.cnt = (uint32_t*)p;
+    return t;
+}
+
+// BATCHED schedule: every bin in one persistent launch.
+struct PersistArgs {
+    uint8_t* pool;            // Q tables of `slots` slots each
+    uint64_t slots;
+    uint32_t Q;               // tables resident at once
+    uint32_t lag;             // dump of rank i is queued after the inserts of rank i+lag (lag < Q)
+    uint32_t n_bins;
+    uint32_t ins_chunk;       // descriptors per insert item (= block size)
+    uint32_t cmp_chunk;       // slots per dump item
+    float load;
+    const uint64_t* bin_off;  // [n_bins+1]
+    const uint64_t* bin_kmers;
+    uint32_t* order;          // [n_bins] rank -> bin, largest bin first
+    uint32_t* nb;             // [n_bins] buckets used by rank
+    uint32_t* n_ins;          // [n_bins] insert items of rank
+    uint32_t* n_cmp;          // [n_bins] dump items of rank
+    uint32_t* ins_done;       // [n_bins]
+    uint32_t* cmp_done;       // [n_bins]
+    uint32_t* seg_code;       // [2 n_bins] (kind << 31) | rank
+    uint64_t* seg_start;      // [2 n_bins + 1] first item of each queue segment
+    uint64_t* cursor;         // work-stealing cursor
+    const uint64_t* n_superm; // descriptors found by the binning
+    uint64_t superm_cap;      // descriptors stored; nothing is scheduled if exceeded
+    uint32_t* status;
+};
+hipError_t launch_plan(const PersistArgs& q, hipStream_t s);
+hipError_t launch_count_persistent(const CountArgs& a, const PersistArgs& q, uint32_t grid, uint32_t block,
+                                   hipStream_t s);
+uint32_t persistent_blocks_per_cu(uint32_t W, uint32_t block);
+
 // PLAIN: insert the k-mers of descriptors [d0, d1) into a table of nb buckets.
 hipError_t launch_count_bin(const CountArgs& a, const Table& t, uint32_t nb, uint64_t d0, uint64_t d1,
                             uint32_t block, hipStream_t s);
