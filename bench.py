@@ -37,6 +37,7 @@ def parse_args(argv=None):
     ap.add_argument("--modes", default="batched,plain")
     ap.add_argument("--pool", type=int, default=0)
     ap.add_argument("--load", type=float, default=0.0)
+    ap.add_argument("--table", default="lds", choices=["lds", "hbm"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     return ap.parse_args(argv)
@@ -133,7 +134,7 @@ def main(argv=None):
     torch.cuda.synchronize()
     bin_map_d = None
     if w.skew_bins:
-        bin_map_d = torch.from_numpy(synth_bin_map(w).view(np.int32)).to(dev)
+        bin_map_d = torch.from_numpy(w.bin_map().view(np.int32)).to(dev)
 
     evs = HipEvents()
     modes = [m.strip() for m in args.modes.split(",") if m.strip()]
@@ -142,7 +143,8 @@ def main(argv=None):
     for mode_name in modes:
         mode = g.GERBIL_BATCHED if mode_name == "batched" else g.GERBIL_PLAIN
         ev = evs.pair()
-        p = g.make_params(w.k, w.m, w.n_bins, w.threshold, mode=mode, pool=args.pool, load_factor=args.load,
+        table = g.GERBIL_TABLE_LDS if args.table == "lds" else g.GERBIL_TABLE_HBM
+        p = g.make_params(w.k, w.m, w.n_bins, w.threshold, mode=mode, pool=args.pool, load_factor=args.load, table=table,
                           bin_map_ptr=bin_map_d.data_ptr() if bin_map_d is not None else 0,
                           timing_events=ctypes.addressof(ev))
         job = g.Job(ascii_d, offsets_d, int(offsets[-1]), p, hist_len=65536)
@@ -194,17 +196,21 @@ def main(argv=None):
         o = results[other]["res"]
         checks["modes_agree"] = bool(o.report.n_out == rep.n_out and np.array_equal(o.hist, R["res"].hist))
 
-    # algorithmic bytes of the persistent counting kernel per launch
+    # Algorithmic bytes of one counting launch: the super-mer bases read
+    # (2 bits per base, n_kmers + k - 1 bases per super-mer), every distinct
+    # entry (key + 32-bit counter, E = 8W + 4 bytes) written once and read
+    # once, and every output pair written once.
     W = (w.k + 31) // 32
     E = 8 * W + 4
-    packed_bytes = 0.25 * (n_valid + rep.n_superm * (w.k - 1))
-    alg_bytes = (8.0 * rep.n_superm + packed_bytes + n_distinct * (2 * E + 12) + (n_valid - n_distinct) * 8.0
-                 + rep.n_out * E)
+    b_in = 0.25 * (n_valid + rep.n_superm * (w.k - 1))
+    alg_bytes = b_in + 2.0 * E * n_distinct + E * rep.n_out
     achieved = alg_bytes / (R["kernel_ms"] / 1000.0) / 1e9
+    kname = {("batched", "lds"): "k_lds_persistent", ("plain", "lds"): "k_lds_stage",
+             ("batched", "hbm"): "k_count_persistent", ("plain", "hbm"): "k_count_bin+k_compact"}[(head, args.table)]
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_count_persistent" if head == "batched" else "k_count_bin+k_compact",
-                "kernel_ms": round(R["kernel_ms"], 3), "alg_bytes": int(alg_bytes)}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kname,
+                "kernel_ms": round(R["kernel_ms"], 3), "alg_bytes": int(alg_bytes),
+                "alg_bytes_per_window": round(alg_bytes / max(1, n_valid), 2)}
 
     cpu = None
     if not args.no_cpu:
@@ -217,7 +223,7 @@ def main(argv=None):
         "config": {"workload": w.name, "description": w.note, "k": w.k, "m": w.m, "n_bins": w.n_bins,
                    "threshold": w.threshold, "reads": int(offsets.size - 1), "bytes": int(ascii_.size),
                    "valid_windows": int(n_valid), "super_mers": int(rep.n_superm), "distinct": n_distinct,
-                   "pairs_out": int(rep.n_out), "schedule": head},
+                   "pairs_out": int(rep.n_out), "schedule": head, "table": args.table},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "p50_ms": percentile(R["step_ms"], 50), "p99_ms": percentile(R["step_ms"], 99),
@@ -231,25 +237,6 @@ def main(argv=None):
         out["batched_over_plain"] = results["plain"]["wall"] / results["batched"]["wall"]
     print(json.dumps(out), flush=True)
     return 0
-
-
-def synth_bin_map(w):
-    """Seeded minimizer -> bin map with log-normal bin weights (skewed bins)."""
-    import numpy as np
-    import synth as s
-    m, nb = w.m, w.n_bins
-    rng = np.random.default_rng(w.seed)
-    weights = np.exp(rng.normal(0.0, 0.97, nb))
-    codes = np.arange(4 ** m)
-    order = rng.permutation(codes)
-    # assign m-mers round-robin weighted by the bin weights
-    share = weights / weights.sum()
-    bounds = np.floor(np.cumsum(share) * codes.size).astype(np.int64)
-    bmap = np.searchsorted(bounds, np.arange(codes.size), side="right").clip(0, nb - 1)
-    out = np.empty(codes.size, dtype=np.uint32)
-    out[order] = bmap.astype(np.uint32)
-    del s
-    return out
 
 
 if __name__ == "__main__":

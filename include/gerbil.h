@@ -73,7 +73,10 @@ enum { GERBIL_PLAIN = 0, GERBIL_BATCHED = 1 };
  * lexicographic order (Fig. 1). */
 enum { GERBIL_ORDER_KMC2 = 0, GERBIL_ORDER_LEX = 1 };
 
-/* Where hash tables live. AUTO lets the library choose per bin. */
+/* Where hash tables live. LDS (and AUTO): every bin, or hash slice of a large
+ * bin, is split by key hash into sub-tables that one workgroup counts in LDS
+ * (the hasher threads of Sec. 2.3.2 with their own tables). HBM: one
+ * open-addressing table per bin in device memory, probed by every workgroup. */
 enum { GERBIL_TABLE_AUTO = 0, GERBIL_TABLE_HBM = 1, GERBIL_TABLE_LDS = 2 };
 
 /* Run parameters; mirrors the command line of App. A. Zero means default. */
@@ -89,8 +92,10 @@ typedef struct {
                                 bin = rank mod n_bins                                             */
     uint32_t mode;           /* GERBIL_PLAIN or GERBIL_BATCHED                                   */
     uint32_t table;          /* GERBIL_TABLE_*                                                   */
-    float load_factor;       /* target distinct keys per slot, (0, 0.95]; 0 = default 0.5        */
-    uint32_t max_probes;     /* theta of Alg. 1: buckets tried before the emergency path; 0 = 8  */
+    float load_factor;       /* k-mers per table slot when tables are sized (k-mers bound the
+                                distinct keys), (0, 0.95]; 0 = default (0.5 HBM, 0.8 LDS)       */
+    uint32_t max_probes;     /* theta of Alg. 1: trials before the emergency path; 0 = default
+                                (8 buckets of 8 slots in HBM tables, 64 slots in LDS tables)     */
     uint32_t block;          /* threads per workgroup for counting, 64..1024; 0 = default        */
     uint32_t pool;           /* BATCHED: hash tables resident at once; 0 = chosen from budget    */
     uint64_t overflow_cap;   /* emergency-area capacity in keys; 0 = default                     */
@@ -199,9 +204,11 @@ int32_t gerbil_bin_workspace(const gerbil_encoded* enc, const gerbil_params* p, 
 int32_t gerbil_bin(const gerbil_encoded* enc, const gerbil_params* p, void* ws, uint64_t ws_bytes,
                    gerbil_bins* out, hipStream_t stream);
 
-/* Workspace bytes gerbil_count needs for these bins. SYNCHRONISES: reads the
- * per-bin k-mer counts from the device to size the hash tables. */
-int32_t gerbil_count_workspace(const gerbil_bins* bins, const gerbil_params* p, uint64_t* bytes);
+/* Workspace bytes gerbil_count needs for these bins. SYNCHRONISES `stream`
+ * (only that stream): reads the per-bin k-mer counts from the device to size
+ * the hash tables, so gerbil_bin must have been enqueued on `stream`. */
+int32_t gerbil_count_workspace(const gerbil_bins* bins, const gerbil_params* p, uint64_t* bytes,
+                               hipStream_t stream);
 
 /* Count the canonical k-mers of every bin (Sec. 2.2, Alg. 1; Sec. 2.3.2;
  * Sec. 3.3.1; Sec. 3.4) and emit the pairs with count >= p->threshold.

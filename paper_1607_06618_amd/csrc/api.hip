@@ -142,11 +142,17 @@ struct CountLayout {
 };
 
 uint64_t slots_for(uint64_t kmers, float load) {
-    // The distinct count of a bin is at most its k-mer count; size for that.
+    // The distinct count of a bin is at most its k-mer count; size for that,
+    // in a power-of-two number of buckets (full-period double hashing).
     double want = (double)kmers / (double)load;
-    uint64_t nb = (uint64_t)(want / kBucket) + 1;
-    if (nb > 0xFFFFFFFFull) nb = 0xFFFFFFFFull;
+    uint64_t nb = next_pow2((uint64_t)(want / kBucket) + 1);
+    if (nb > (1ull << 31)) nb = 1ull << 31;
     return nb * kBucket;
+}
+uint64_t prev_pow2(uint64_t x) {
+    uint64_t n = 1;
+    while (n * 2 <= x) n *= 2;
+    return n;
 }
 
 // Everything but the table pool.
@@ -180,6 +186,79 @@ uint32_t pool_size(const gerbil_params* p) {
     return std::min(q, p->n_bins);
 }
 float load_of(const gerbil_params* p) { return p->load_factor > 0 ? p->load_factor : kDefaultLoad; }
+bool use_lds(const gerbil_params* p) { return p->table != GERBIL_TABLE_HBM; }
+
+constexpr uint32_t kDefaultKeySlots = 8;
+constexpr uint32_t kDefaultLdsTheta = 64;   // single-slot probes are cheap in LDS
+constexpr double kDefaultLdsFill = 0.8;     // k-mers per LDS slot (distinct keys are fewer)
+
+struct LdsSizing {
+    uint32_t C, target, ranks_cap, Q, lag;
+    uint64_t sp_cap;
+};
+
+LdsSizing lds_sizing(const gerbil_params* p, uint64_t n_bytes) {
+    LdsSizing z;
+    const uint32_t W = words_for(p->k);
+    z.C = lds_table_slots(W);
+    const double fill = p->load_factor > 0 ? p->load_factor : kDefaultLdsFill;
+    z.target = std::max<uint32_t>(64, (uint32_t)((double)z.C * fill));
+    const uint64_t per_slice = (uint64_t)kLdsMaxSub * z.target;
+    z.ranks_cap = (uint32_t)std::min<uint64_t>(p->n_bins + n_bytes / per_slice + 1, 1u << 20);
+    z.sp_cap = n_bytes / z.target + 2ull * z.ranks_cap + 1;
+    if (p->mode == GERBIL_BATCHED) {
+        uint32_t q = p->pool ? p->pool : kDefaultKeySlots;
+        z.Q = std::max<uint32_t>(1, std::min(q, z.ranks_cap));
+    } else {
+        z.Q = 1;
+    }
+    z.lag = z.Q / 2;
+    return z;
+}
+
+// Keys a slot must hold: the largest rank (bin, or hash slice of a bin) with slack for hash variance.
+uint64_t lds_slot_keys(uint64_t max_kmers, const LdsSizing& z) {
+    const uint64_t per_slice = (uint64_t)kLdsMaxSub * z.target;
+    uint64_t V = (max_kmers + per_slice - 1) / per_slice;
+    if (V <= 1) return std::max<uint64_t>(max_kmers, 1);
+    uint64_t est = (uint64_t)((double)max_kmers / (double)V * 1.25) + 65536;
+    return std::min(est, max_kmers);
+}
+
+struct LdsLayout {
+    uint32_t *n_ranks, *rank_bin, *rank_slice, *rank_nslice, *rank_nsub, *rank_nchunk;
+    uint64_t *rank_spbase, *rank_keys;
+    uint32_t *sp_cnt, *sp_cur;
+    uint64_t* sp_off;
+    uint32_t* done;
+    uint64_t* seg_start;
+    uint32_t* n_seg;
+    uint64_t* cursor;
+    uint64_t* keys;
+};
+
+uint64_t lds_fixed(const LdsSizing& z, void* ws, uint64_t start, LdsLayout* L) {
+    Carve c(ws ? (uint8_t*)ws + start : nullptr);
+    LdsLayout l;
+    l.n_ranks = c.take<uint32_t>(4);
+    l.rank_bin = c.take<uint32_t>(z.ranks_cap);
+    l.rank_slice = c.take<uint32_t>(z.ranks_cap);
+    l.rank_nslice = c.take<uint32_t>(z.ranks_cap);
+    l.rank_nsub = c.take<uint32_t>(z.ranks_cap);
+    l.rank_nchunk = c.take<uint32_t>(z.ranks_cap);
+    l.rank_spbase = c.take<uint64_t>(z.ranks_cap);
+    l.rank_keys = c.take<uint64_t>(z.ranks_cap);
+    l.sp_cnt = c.take<uint32_t>(z.sp_cap);
+    l.sp_cur = c.take<uint32_t>(z.sp_cap);
+    l.sp_off = c.take<uint64_t>(z.sp_cap);
+    l.done = c.take<uint32_t>(4ull * z.ranks_cap);
+    l.seg_start = c.take<uint64_t>(4ull * ((uint64_t)z.ranks_cap + 3 + z.lag) + 1);
+    l.n_seg = c.take<uint32_t>(4);
+    l.cursor = c.take<uint64_t>(4);
+    l.keys = ws ? (uint64_t*)((uint8_t*)ws + start + c.used) : nullptr;
+    if (L) *L = l;
+    return c.used;
+}
 
 int32_t hip_status(hipError_t e) { return e == hipSuccess ? GERBIL_OK : GERBIL_EDEVICE; }
 
@@ -196,6 +275,131 @@ __global__ void k_fold_hist(const uint64_t* __restrict__ hist, uint32_t len, uin
         __syncthreads();
     }
     if (tid == 0) out[len - 1] = part[0];
+}
+
+void fill_state(gerbil_counted* state, const gerbil_params* p, const gerbil_bins* bins, uint64_t cap, uint64_t ovf_cap,
+                const CountLayout& L) {
+    memset(state, 0, sizeof(*state));
+    state->k = p->k;
+    state->W = words_for(p->k);
+    state->threshold = p->threshold;
+    state->hist_len = kHistInternal;
+    state->cap = cap;
+    state->overflow_cap = ovf_cap;
+    state->n_out = L.scalars;
+    state->n_overflow = L.scalars + 1;
+    state->max_count = L.scalars + 2;
+    state->status = (uint32_t*)(L.scalars + 3);
+    state->hist = L.hist;
+    state->n_superm = bins->n_superm;
+    state->bin_status = bins->status;
+}
+
+CountArgs count_args(const gerbil_params* p, const gerbil_bins* bins, const gerbil_counted* state, uint64_t* keys,
+                     uint32_t* counts, uint64_t cap, const CountLayout& L) {
+    CountArgs a;
+    a.packed = bins->packed;
+    a.n_bytes = bins->n_bytes;
+    a.desc = bins->desc;
+    a.k = p->k;
+    a.W = words_for(p->k);
+    a.threshold = p->threshold;
+    a.theta = p->max_probes ? p->max_probes : kDefaultTheta;
+    a.seed = kHashSeed;
+    a.ovf_keys = L.ovf_keys;
+    a.ovf_cap = state->overflow_cap;
+    a.n_ovf = state->n_overflow;
+    a.out_keys = keys;
+    a.out_counts = counts;
+    a.cap = cap;
+    a.n_out = state->n_out;
+    a.hist = L.hist;
+    a.max_count = state->max_count;
+    a.status = state->status;
+    return a;
+}
+
+// LDS sub-table path: plan on the device, then one persistent launch
+// (BATCHED) or four launches per rank (PLAIN).
+int32_t count_lds(const gerbil_bins* bins, const gerbil_params* p, void* ws, uint64_t ws_bytes, uint64_t* keys,
+                  uint32_t* counts, uint64_t cap, gerbil_counted* state, hipStream_t stream) {
+    const uint32_t W = words_for(p->k);
+    const bool batched = p->mode == GERBIL_BATCHED;
+    const uint64_t ovf_cap = ovf_capacity(p);
+    const LdsSizing z = lds_sizing(p, bins->n_bytes);
+    CountLayout L;
+    const uint64_t fixed0 = count_fixed(W, ovf_cap, p->n_bins, false, ws, &L);
+    LdsLayout LL;
+    const uint64_t fixed = fixed0 + lds_fixed(z, ws, fixed0, &LL);
+    if (fixed + kAlign > ws_bytes) return GERBIL_EINVAL;
+    uint64_t slot_keys = (ws_bytes - fixed - kAlign) / ((uint64_t)z.Q * 8ull * W);
+    if (slot_keys < 1) return GERBIL_EINVAL;
+    if (slot_keys > 0xFFFFFFFFull) slot_keys = 0xFFFFFFFFull;   // run offsets are 32-bit inside a slot
+    fill_state(state, p, bins, cap, ovf_cap, L);
+    CountArgs a = count_args(p, bins, state, keys, counts, cap, L);
+
+    LdsArgs l;
+    l.n_bins = p->n_bins;
+    l.ranks_cap = z.ranks_cap;
+    l.n_ranks = LL.n_ranks;
+    l.rank_bin = LL.rank_bin;
+    l.rank_slice = LL.rank_slice;
+    l.rank_nslice = LL.rank_nslice;
+    l.rank_nsub = LL.rank_nsub;
+    l.rank_nchunk = LL.rank_nchunk;
+    l.rank_spbase = LL.rank_spbase;
+    l.rank_keys = LL.rank_keys;
+    l.sp_cap = z.sp_cap;
+    l.sp_cnt = LL.sp_cnt;
+    l.sp_off = LL.sp_off;
+    l.sp_cur = LL.sp_cur;
+    l.keys = LL.keys;
+    l.slot_keys = slot_keys;
+    l.Q = z.Q;
+    l.lag = z.lag;
+    l.target = z.target;
+    l.table_slots = z.C;
+    l.theta = p->max_probes ? p->max_probes : kDefaultLdsTheta;
+    l.bin_off = bins->bin_off;
+    l.bin_kmers = bins->bin_kmers;
+    l.done = LL.done;
+    l.seg_start = LL.seg_start;
+    l.n_seg = LL.n_seg;
+    l.cursor = LL.cursor;
+    l.n_superm = bins->n_superm;
+    l.superm_cap = bins->cap_superm;
+    l.status = state->status;
+
+    hipError_t e = launch_fill_u64(L.scalars, 8, 0, stream);
+    if (e == hipSuccess) e = launch_fill_u64(L.hist, kHistInternal, 0, stream);
+    if (e == hipSuccess) e = launch_lds_plan(l, stream);
+    if (e != hipSuccess) return GERBIL_EDEVICE;
+    if (batched) {
+        if (p->timing_events) e = hipEventRecord(p->timing_events[0], stream);
+        if (e == hipSuccess) e = launch_lds_persistent(a, l, (uint32_t)device_cus(), stream);
+        if (e == hipSuccess && p->timing_events) e = hipEventRecord(p->timing_events[1], stream);
+    } else {
+        uint32_t n_ranks = 0;
+        e = hipMemcpyAsync(&n_ranks, LL.n_ranks, 4, hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        std::vector<uint32_t> nchunk(n_ranks), nsub(n_ranks);
+        if (e == hipSuccess && n_ranks) {
+            e = hipMemcpyAsync(nchunk.data(), LL.rank_nchunk, 4ull * n_ranks, hipMemcpyDeviceToHost, stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(nsub.data(), LL.rank_nsub, 4ull * n_ranks, hipMemcpyDeviceToHost, stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        }
+        if (e == hipSuccess && p->timing_events) e = hipEventRecord(p->timing_events[0], stream);
+        for (uint32_t r = 0; r < n_ranks && e == hipSuccess; r++) {
+            if (!nchunk[r]) continue;
+            e = launch_lds_stage(a, l, 0, r, nchunk[r], stream);
+            if (e == hipSuccess) e = launch_lds_stage(a, l, 1, r, 1, stream);
+            if (e == hipSuccess) e = launch_lds_stage(a, l, 2, r, nchunk[r], stream);
+            if (e == hipSuccess) e = launch_lds_stage(a, l, 3, r, nsub[r], stream);
+        }
+        if (e == hipSuccess && p->timing_events) e = hipEventRecord(p->timing_events[1], stream);
+    }
+    if (e == hipSuccess) e = launch_overflow(a, stream);
+    return hip_status(e);
 }
 
 }  // namespace
@@ -316,17 +520,26 @@ int32_t gerbil_bin(const gerbil_encoded* enc, const gerbil_params* p, void* ws, 
     return hip_status(e);
 }
 
-int32_t gerbil_count_workspace(const gerbil_bins* bins, const gerbil_params* p, uint64_t* bytes) {
+int32_t gerbil_count_workspace(const gerbil_bins* bins, const gerbil_params* p, uint64_t* bytes,
+                               hipStream_t stream) {
     int32_t st = check_params(p);
     if (st) return st;
     if (!bytes || !bins || p->k != bins->k || p->n_bins != bins->n_bins) return GERBIL_EINVAL;
     std::vector<uint64_t> kmers(bins->n_bins);
-    if (hipDeviceSynchronize() != hipSuccess) return GERBIL_EDEVICE;
-    if (hipMemcpy(kmers.data(), bins->bin_kmers, 8 * (size_t)bins->n_bins, hipMemcpyDeviceToHost) != hipSuccess)
+    if (hipMemcpyAsync(kmers.data(), bins->bin_kmers, 8 * (size_t)bins->n_bins, hipMemcpyDeviceToHost, stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
         return GERBIL_EDEVICE;
     uint64_t mx = 1;
     for (uint64_t v : kmers) mx = std::max(mx, v);
     const uint32_t W = words_for(p->k);
+    if (use_lds(p)) {
+        LdsSizing z = lds_sizing(p, bins->n_bytes);
+        uint64_t fixed = count_fixed(W, ovf_capacity(p), p->n_bins, false, nullptr, nullptr);
+        fixed += lds_fixed(z, nullptr, 0, nullptr);
+        *bytes = fixed + (uint64_t)z.Q * lds_slot_keys(mx, z) * 8ull * W + kAlign;
+        return GERBIL_OK;
+    }
     const uint64_t slots = slots_for(mx, load_of(p));
     *bytes = count_fixed(W, ovf_capacity(p), p->n_bins, p->mode == GERBIL_BATCHED, nullptr, nullptr) +
              (uint64_t)pool_size(p) * pool_table_bytes(slots, W);
@@ -345,6 +558,7 @@ int32_t gerbil_count(const gerbil_bins* bins, const gerbil_params* p, void* ws, 
     const bool batched = p->mode == GERBIL_BATCHED;
     const float load = load_of(p);
     const uint64_t ovf_cap = ovf_capacity(p);
+    if (use_lds(p)) return count_lds(bins, p, ws, ws_bytes, keys, counts, cap, state, stream);
     const uint32_t Q = pool_size(p);
     CountLayout L;
     const uint64_t fixed = count_fixed(W, ovf_cap, n_bins, batched, ws, &L);
@@ -455,8 +669,7 @@ int32_t gerbil_count(const gerbil_bins* bins, const gerbil_params* p, void* ws, 
         for (uint32_t b = 0; b < n_bins && e == hipSuccess; b++) {
             uint64_t d0 = off[b], d1 = off[b + 1];
             if (d1 <= d0) continue;
-            uint64_t want = std::min<uint64_t>(slots_for(kmers[b], load), slots);
-            uint32_t nb = (uint32_t)(want / kBucket);
+            uint32_t nb = (uint32_t)std::min<uint64_t>(slots_for(kmers[b], load) / kBucket, prev_pow2(slots / kBucket));
             e = launch_count_bin(a, t, nb, d0, d1, block, stream);
             if (e == hipSuccess) e = launch_compact(a, t, nb, stream);
         }

@@ -57,7 +57,8 @@ __global__ void __launch_bounds__(kPlanBlock) k_plan(PersistArgs q) {
             __syncthreads();
         }
     }
-    const uint64_t max_nb = q.slots / kBucket;
+    uint64_t max_nb = 1;   // largest power of two of buckets that fits a pool table
+    while (max_nb * 2 <= q.slots / kBucket) max_nb *= 2;
     const uint32_t L = q.lag < n ? q.lag : n;
     // descriptors beyond the capacity were never stored: schedule nothing
     const bool overfull = *q.n_superm > q.superm_cap;
@@ -68,7 +69,9 @@ __global__ void __launch_bounds__(kPlanBlock) k_plan(PersistArgs q) {
         uint64_t nd = q.bin_off[b + 1] - q.bin_off[b];
         uint64_t km = q.bin_kmers[b];
         uint64_t want = (uint64_t)((double)km / (double)q.load / kBucket) + 1;
-        uint32_t nbk = (uint32_t)(want < max_nb ? want : max_nb);
+        uint64_t p2 = 1;
+        while (p2 < want) p2 *= 2;
+        uint32_t nbk = (uint32_t)(p2 < max_nb ? p2 : max_nb);
         uint32_t ni = overfull ? 0u : (uint32_t)((nd + q.ins_chunk - 1) / q.ins_chunk);
         uint32_t nc = (nd && !overfull) ? (uint32_t)(((uint64_t)nbk * kBucket + q.cmp_chunk - 1) / q.cmp_chunk) : 0u;
         q.order[i] = b;
@@ -117,28 +120,6 @@ hipError_t launch_plan(const PersistArgs& q, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Wait (one thread) until *ctr >= target; bounded. Polls with relaxed
-// loads (no cache maintenance per poll) and acquires once at the end.
-__device__ __forceinline__ void wait_at_least(const uint32_t* ctr, uint32_t target, uint32_t* status) {
-    uint32_t spins = 0;
-    while (ld_dev(ctr) < target) {
-        if (++spins > kWaitLimit) {
-            set_status(status, ST_SPIN);
-            break;
-        }
-        __builtin_amdgcn_s_sleep(2);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-}
-
-// Make every thread's table writes visible at agent scope, then count the
-// item as done.
-__device__ __forceinline__ void finish_item(uint32_t* ctr) {
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 template <int W>
 __global__ void __launch_bounds__(256) k_count_persistent(CountArgs a, PersistArgs q) {
     constexpr uint32_t B = 256;
@@ -149,6 +130,7 @@ __global__ void __launch_bounds__(256) k_count_persistent(CountArgs a, PersistAr
     __shared__ uint64_t s_item;
     __shared__ uint32_t s_seg;
     const uint32_t tid = threadIdx.x;
+    if (tid == 0) s_seg = 0;
     for (uint32_t b = tid; b < kLdsHist; b += B) lh[b] = 0;
     uint32_t wmax = 0;
     const uint32_t ns = 2 * q.n_bins;
@@ -157,14 +139,7 @@ __global__ void __launch_bounds__(256) k_count_persistent(CountArgs a, PersistAr
         if (tid == 0) {
             uint64_t item = add_dev(q.cursor, 1ull);
             s_item = item;
-            if (item < total) {
-                uint32_t lo = 0, hi = ns;   // last segment whose start <= item
-                while (hi - lo > 1) {
-                    uint32_t mid = (lo + hi) >> 1;
-                    if (q.seg_start[mid] <= item) lo = mid; else hi = mid;
-                }
-                s_seg = lo;
-            }
+            if (item < total) s_seg = find_segment(q.seg_start, ns, item, s_seg);
         }
         __syncthreads();
         const uint64_t item = s_item;
@@ -178,7 +153,7 @@ __global__ void __launch_bounds__(256) k_count_persistent(CountArgs a, PersistAr
         const Table t = pool_table(q.pool, q.slots, W, rank % q.Q);
         if (!(code >> 31)) {
             // insert item: needs a clean table
-            if (tid == 0 && rank >= q.Q) wait_at_least(q.cmp_done + (rank - q.Q), q.n_cmp[rank - q.Q], a.status);
+            if (tid == 0 && rank >= q.Q) wait_done(q.cmp_done + (rank - q.Q), q.n_cmp[rank - q.Q], kWaitLimit, a.status, ST_SPIN);
             __syncthreads();
             const uint64_t d_end = q.bin_off[bin + 1];
             const uint64_t i = q.bin_off[bin] + local * q.ins_chunk + tid;
@@ -202,10 +177,10 @@ __global__ void __launch_bounds__(256) k_count_persistent(CountArgs a, PersistAr
                 }
                 count_position<W>(a, t, nb, sstart[lo] + (int64_t)(idx - spre[lo]));
             }
-            finish_item(q.ins_done + rank);
+            signal_done(q.ins_done + rank);
         } else {
             // dump item: needs every insert of this rank
-            if (tid == 0) wait_at_least(q.ins_done + rank, q.n_ins[rank], a.status);
+            if (tid == 0) wait_done(q.ins_done + rank, q.n_ins[rank], kWaitLimit, a.status, ST_SPIN);
             __syncthreads();
             const uint64_t s0 = local * q.cmp_chunk;
             uint64_t s1 = s0 + q.cmp_chunk;
@@ -215,7 +190,7 @@ __global__ void __launch_bounds__(256) k_count_persistent(CountArgs a, PersistAr
                 uint64_t slot = base + tid;
                 compact_slot<W>(a, t, slot, slot < s1, lh, wmax);
             }
-            finish_item(q.cmp_done + rank);
+            signal_done(q.cmp_done + rank);
         }
         __syncthreads();
     }

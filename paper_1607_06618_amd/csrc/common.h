@@ -125,6 +125,52 @@ __device__ __forceinline__ T cas_dev(T* p, U expected_in, V desired) {
                                          __HIP_MEMORY_SCOPE_AGENT);
     return expected;  // the value found (== old expected on success)
 }
+// Wait until every memory operation this wave issued has been performed
+// (loads returned, stores and atomics acknowledged). Also a compiler barrier.
+__device__ __forceinline__ void drain_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Item hand-off between workgroups: every thread drains its device-coherent
+// writes, the block meets, then one thread raises the done counter.
+__device__ __forceinline__ void signal_done(uint32_t* ctr) {
+    drain_memory();
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait (one thread) until *ctr >= target; bounded by `limit` polls (sets
+// `bit` in *status on give-up). Data guarded by the counter is read with
+// device-coherent loads afterwards.
+__device__ __forceinline__ void wait_done(const uint32_t* ctr, uint32_t target, uint32_t limit, uint32_t* status,
+                                          uint32_t bit) {
+    uint32_t spins = 0;
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (++spins > limit) {
+            __hip_atomic_fetch_or(status, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    asm volatile("" ::: "memory");
+}
+
+// Segment of a work item: last j with start[j] <= item, searched forward from
+// `hint` (items are popped in increasing order, so a workgroup's segments
+// never decrease) by galloping, then bisection.
+__device__ __forceinline__ uint32_t find_segment(const uint64_t* start, uint32_t ns, uint64_t item, uint32_t hint) {
+    uint32_t lo = hint, step = 1, hi = lo + 1;
+    while (hi < ns && start[hi] <= item) {
+        lo = hi;
+        hi = lo + step;
+        step <<= 1;
+    }
+    if (hi > ns) hi = ns;
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (start[mid] <= item) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
 __device__ __forceinline__ void set_status(uint32_t* status, uint32_t bits) {
     __hip_atomic_fetch_or(status, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

@@ -115,6 +115,61 @@ hipError_t launch_count_persistent(const CountArgs& a, const PersistArgs& q, uin
                                    hipStream_t s);
 uint32_t persistent_blocks_per_cu(uint32_t W, uint32_t block);
 
+// LDS sub-table path. A rank is one hash slice of a bin (bins too large for
+// kLdsMaxSub sub-tables are cut into slices by the high hash bits); a rank
+// has P sub-tables, each counted by one workgroup in LDS.
+constexpr uint32_t kLdsBlock = 1024;            // threads per workgroup (one workgroup per CU)
+constexpr uint32_t kLdsBytes = 160 * 1024;      // dynamic LDS per workgroup
+constexpr uint32_t kLdsMaxSub = 4096;           // sub-tables per rank (LDS of the scatter stage)
+constexpr uint32_t kLdsReserved = 2048;         // LDS kept for the histogram and scalars
+// Slots of an LDS table: the largest prime that fits, so that double hashing
+// has a full period.
+constexpr uint32_t kLdsTableScratch = 256;      // scan scratch of the table stage after its slots
+inline uint32_t lds_table_slots(uint32_t W) {
+    uint32_t c = (kLdsBytes - kLdsReserved - kLdsTableScratch) / (8 * W + 4);
+    for (;; c--) {
+        bool prime = c > 2;
+        for (uint32_t d = 2; prime && d * d <= c; d++) prime = c % d != 0;
+        if (prime) return c;
+    }
+}
+
+struct LdsArgs {
+    uint32_t n_bins, ranks_cap;
+    uint32_t* n_ranks;        // scalar (plan output)
+    uint32_t* rank_bin;       // [ranks_cap]
+    uint32_t* rank_slice;
+    uint32_t* rank_nslice;
+    uint32_t* rank_nsub;      // P (0 for an empty bin)
+    uint32_t* rank_nchunk;    // descriptor chunks of kLdsBlock
+    uint64_t* rank_spbase;    // first sub-table of the rank
+    uint64_t* rank_keys;      // keys of the rank (scan output)
+    uint64_t sp_cap;
+    uint32_t* sp_cnt;         // [sp_cap] keys per sub-table
+    uint64_t* sp_off;         // [sp_cap] first key of a sub-table inside its key slot
+    uint32_t* sp_cur;         // [sp_cap] scatter cursors
+    uint64_t* keys;           // Q key slots of slot_keys keys (W words each)
+    uint64_t slot_keys;
+    uint32_t Q, lag;
+    uint32_t target;          // keys per sub-table
+    uint32_t table_slots;     // LDS slots per sub-table
+    uint32_t theta;           // probes per key before the emergency area
+    const uint64_t* bin_off;
+    const uint64_t* bin_kmers;
+    uint32_t* done;           // [4 * ranks_cap] finished items per (rank, stage)
+    uint64_t* seg_start;      // [4 * (ranks_cap + 3 + lag) + 1]
+    uint32_t* n_seg;          // scalar
+    uint64_t* cursor;
+    const uint64_t* n_superm;
+    uint64_t superm_cap;
+    uint32_t* status;
+};
+hipError_t launch_lds_plan(const LdsArgs& l, hipStream_t s);
+hipError_t launch_lds_persistent(const CountArgs& a, const LdsArgs& l, uint32_t grid, hipStream_t s);
+// PLAIN: one stage of one rank (stage 0 count, 1 scan, 2 scatter, 3 LDS count + dump), `items` blocks.
+hipError_t launch_lds_stage(const CountArgs& a, const LdsArgs& l, uint32_t stage, uint32_t rank, uint32_t items,
+                            hipStream_t s);
+
 // PLAIN: insert the k-mers of descriptors [d0, d1) into a table of nb buckets.
 hipError_t launch_count_bin(const CountArgs& a, const Table& t, uint32_t nb, uint64_t d0, uint64_t d1,
                             uint32_t block, hipStream_t s);

@@ -1,0 +1,774 @@
+// LDS sub-table counting (the default table placement).
+//
+// Phase two of the paper splits the k-mers of a temporary file over several
+// hasher threads by a hash of the k-mer, each with its own table
+// (Sec. 2.3.2, step 2). Here a hasher is a workgroup and its table lives in
+// the 160 KB of LDS of one CU. For every rank (a bin, or a hash slice of a
+// very large bin) four stages run:
+//   A  count:   every k-mer of the bin is extracted, canonicalised and hashed;
+//               the keys of this slice are counted per sub-table (LDS
+//               histogram, one global add per sub-table and chunk);
+//   S  scan:    prefix of the sub-table sizes -> contiguous key runs;
+//   C  scatter: the keys are extracted again and written to their sub-table
+//               run (LDS ranks, one global reservation per sub-table and
+//               round), so every run is contiguous in HBM;
+//   D  count:   one workgroup streams a run through an open-addressing LDS
+//               table (Alg. 1: CAS on word 0, publish the other words, add to
+//               the counter; theta probes, then the emergency area), then
+//               dumps it (threshold, histogram).
+// HBM traffic is streaming (keys written once and read once), and all table
+// atomics stay inside one CU.
+#include "table.h"
+
+namespace gerbil {
+
+constexpr uint32_t kLdsSpin = 1u << 20;     // bounded wait for an unpublished LDS slot
+constexpr uint32_t kLdsWait = 1u << 25;     // bounded wait between work items
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+
+__device__ __forceinline__ uint32_t slice_of(uint64_t h, uint32_t V) { return fastrange32((uint32_t)(h >> 32), V); }
+__device__ __forceinline__ uint32_t sub_of(uint64_t h, uint32_t P) { return fastrange32((uint32_t)h, P); }
+__device__ __forceinline__ uint64_t lds_hash(uint64_t h) { return fmix64(h ^ 0x5851F42D4C957F2Dull); }
+
+// ----------------------------------------------------------------- plan
+// One workgroup. Ranks follow the bins in LPT order (largest first); a bin
+// with more k-mers than kLdsMaxSub sub-tables of `target` keys is cut into
+// V slices. Queue segment 4*tick + stage holds stage `stage` of rank
+// tick - lag[stage], lag = {0, 1, 2, 2 + L}: every dependency of an item is
+// in an earlier segment.
+__global__ void __launch_bounds__(1024) k_lds_plan(LdsArgs l) {
+    __shared__ uint64_t skey[kMaxBins];
+    __shared__ uint32_t sval[kMaxBins];
+    __shared__ uint64_t part[1024];
+    __shared__ uint32_t s_total;
+    const uint32_t tid = threadIdx.x, n = l.n_bins;
+    uint32_t N = 1;
+    while (N < n) N <<= 1;
+    for (uint32_t i = tid; i < N; i += 1024) {
+        skey[i] = i < n ? l.bin_kmers[i] : 0ull;
+        sval[i] = i;
+    }
+    __syncthreads();
+    for (uint32_t size = 2; size <= N; size <<= 1) {
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            for (uint32_t i = tid; i < N / 2; i += 1024) {
+                uint32_t lo = 2 * stride * (i / stride) + (i % stride), hi = lo + stride;
+                bool desc = (lo & size) == 0;
+                bool lo_first = skey[lo] > skey[hi] || (skey[lo] == skey[hi] && sval[lo] < sval[hi]);
+                if (desc != lo_first) {
+                    uint64_t tk = skey[lo]; skey[lo] = skey[hi]; skey[hi] = tk;
+                    uint32_t tv = sval[lo]; sval[lo] = sval[hi]; sval[hi] = tv;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const bool overfull = *l.n_superm > l.superm_cap;
+    const uint64_t per_slice = (uint64_t)kLdsMaxSub * l.target;
+    // 1. slices per bin (in LPT order) and their prefix -> first rank of each bin
+    auto slices = [&](uint32_t i) -> uint64_t {
+        uint64_t km = skey[i];
+        uint64_t v = (km + per_slice - 1) / per_slice;
+        return v ? v : 1;
+    };
+    const uint32_t per = (n + 1023) / 1024;
+    uint64_t sum = 0;
+    for (uint32_t e = 0; e < per; e++) {
+        uint32_t i = tid * per + e;
+        if (i < n) sum += slices(i);
+    }
+    part[tid] = sum;
+    __syncthreads();
+    for (uint32_t off = 1; off < 1024; off <<= 1) {
+        uint64_t y = tid >= off ? part[tid - off] : 0ull;
+        __syncthreads();
+        part[tid] += y;
+        __syncthreads();
+    }
+    const uint64_t n_ranks = part[1023];
+    const bool too_many = n_ranks > l.ranks_cap;
+    if (tid == 0 && (too_many || overfull)) set_status(l.status, too_many ? ST_POOL : ST_SUPERM_CAP);
+    if (!too_many) {
+        uint64_t r = tid ? part[tid - 1] : 0ull;
+        for (uint32_t e = 0; e < per; e++) {
+            uint32_t i = tid * per + e;
+            if (i >= n) break;
+            uint32_t b = sval[i];
+            uint64_t V = slices(i);
+            uint64_t nd = l.bin_off[b + 1] - l.bin_off[b];
+            uint64_t kest = (skey[i] + V - 1) / V;
+            uint64_t P = (kest + l.target - 1) / l.target;
+            if (P < 1) P = 1;
+            if (P > kLdsMaxSub) P = kLdsMaxSub;
+            bool empty = nd == 0 || overfull;
+            for (uint64_t v = 0; v < V; v++, r++) {
+                l.rank_bin[r] = b;
+                l.rank_slice[r] = (uint32_t)v;
+                l.rank_nslice[r] = (uint32_t)V;
+                l.rank_nsub[r] = empty ? 0u : (uint32_t)P;
+                l.rank_nchunk[r] = empty ? 0u : (uint32_t)((nd + kLdsBlock - 1) / kLdsBlock);
+            }
+        }
+    }
+    if (tid == 0) {
+        *l.n_ranks = too_many ? 0u : (uint32_t)n_ranks;
+        s_total = too_many ? 0u : (uint32_t)n_ranks;
+    }
+    __threadfence();
+    __syncthreads();
+    const uint32_t R = s_total;
+    // 2. first sub-table of every rank; zero the per-rank state
+    const uint32_t rper = (R + 1023) / 1024;
+    sum = 0;
+    for (uint32_t e = 0; e < rper; e++) {
+        uint32_t r = tid * rper + e;
+        if (r < R) sum += l.rank_nsub[r];
+    }
+    part[tid] = sum;
+    __syncthreads();
+    for (uint32_t off = 1; off < 1024; off <<= 1) {
+        uint64_t y = tid >= off ? part[tid - off] : 0ull;
+        __syncthreads();
+        part[tid] += y;
+        __syncthreads();
+    }
+    const bool sp_over = part[1023] > l.sp_cap;
+    if (tid == 0 && sp_over) set_status(l.status, ST_POOL);
+    uint64_t base = tid ? part[tid - 1] : 0ull;
+    for (uint32_t e = 0; e < rper; e++) {
+        uint32_t r = tid * rper + e;
+        if (r >= R) break;
+        if (sp_over) l.rank_nsub[r] = 0, l.rank_nchunk[r] = 0;
+        l.rank_spbase[r] = base;
+        l.rank_keys[r] = 0;
+        base += l.rank_nsub[r];
+        for (int s = 0; s < 4; s++) l.done[4 * r + s] = 0;
+    }
+    __threadfence();
+    __syncthreads();
+    const uint64_t n_sp = sp_over ? 0 : part[1023];
+    for (uint64_t j = tid; j < n_sp; j += 1024) {
+        l.sp_cnt[j] = 0;
+        l.sp_cur[j] = 0;
+    }
+    // 3. queue segments: items per segment, then their prefix
+    const uint32_t L = l.lag;
+    const uint32_t ticks = R + 3 + L;
+    const uint32_t ns = 4 * ticks;
+    const uint32_t lag[4] = {0u, 1u, 2u, 2u + L};
+    const uint32_t sper = (ns + 1023) / 1024;
+    auto items = [&](uint32_t seg) -> uint64_t {
+        uint32_t st = seg & 3, tick = seg >> 2;
+        if (tick < lag[st]) return 0;
+        uint32_t r = tick - lag[st];
+        if (r >= R) return 0;
+        uint32_t nc = l.rank_nchunk[r];
+        if (nc == 0) return 0;
+        switch (st) {
+            case 0: return nc;
+            case 1: return 1;
+            case 2: return nc;
+            default: return l.rank_nsub[r];
+        }
+    };
+    sum = 0;
+    for (uint32_t e = 0; e < sper; e++) {
+        uint32_t j = tid * sper + e;
+        if (j < ns) sum += items(j);
+    }
+    part[tid] = sum;
+    __syncthreads();
+    for (uint32_t off = 1; off < 1024; off <<= 1) {
+        uint64_t y = tid >= off ? part[tid - off] : 0ull;
+        __syncthreads();
+        part[tid] += y;
+        __syncthreads();
+    }
+    uint64_t run = tid ? part[tid - 1] : 0ull;
+    for (uint32_t e = 0; e < sper; e++) {
+        uint32_t j = tid * sper + e;
+        if (j < ns) {
+            l.seg_start[j] = run;
+            run += items(j);
+        }
+    }
+    if (tid == 1023) {
+        l.seg_start[ns] = part[1023];
+        *l.n_seg = ns;
+        *l.cursor = 0;
+    }
+}
+
+hipError_t launch_lds_plan(const LdsArgs& l, hipStream_t s) {
+    hipLaunchKernelGGL(k_lds_plan, dim3(1), dim3(1024), 0, s, l);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------- LDS layout
+struct Lds {
+    uint32_t* hist;     // [kLdsHist] count-of-counts, flushed at the end of the kernel
+    uint8_t* u;         // union region, carved per stage
+};
+__device__ __forceinline__ Lds lds_carve(uint8_t* base) {
+    Lds x;
+    x.hist = (uint32_t*)base;
+    x.u = base + kLdsReserved;
+    return x;
+}
+
+// Descriptor chunk `chunk` of bin b: one descriptor per thread; exclusive
+// prefix of the k-mer counts in spre[0..kLdsBlock] (spre[kLdsBlock] = total),
+// first positions in sstart.
+__device__ __forceinline__ uint32_t load_chunk(const CountArgs& a, const LdsArgs& l, uint32_t b, uint32_t chunk,
+                                               int64_t* sstart, uint32_t* spre, uint32_t* wsum) {
+    const uint32_t tid = threadIdx.x;
+    const uint64_t d_end = l.bin_off[b + 1];
+    const uint64_t i = l.bin_off[b] + (uint64_t)chunk * kLdsBlock + tid;
+    uint32_t n = 0;
+    int64_t st = 0;
+    if (i < d_end) {
+        uint64_t d = a.desc[i];
+        st = (int64_t)(d >> 24);
+        n = (uint32_t)(d & 0xFFFFFFu);
+    }
+    uint32_t total;
+    uint32_t pre = block_excl_scan(n, wsum, total);
+    sstart[tid] = st;
+    spre[tid] = pre;
+    if (tid == 0) spre[kLdsBlock] = total;
+    __syncthreads();
+    return total;
+}
+
+// A rolling window over consecutive k-mers of a chunk: the forward and
+// reverse-complement keys are shifted by one base per k-mer (Sec. 2.3.2
+// splitter step) instead of being re-read from the packed reads.
+template <int W>
+struct Roller {
+    uint64_t fw[W], rc[W];
+    int64_t p;        // position of the current k-mer
+    uint32_t next;    // chunk k-mer index at which the next super-mer starts
+    bool ok;          // the super-mer lies inside the reads
+};
+
+template <int W>
+__device__ __forceinline__ void roll_seek(const CountArgs& a, const int64_t* sstart, const uint32_t* spre, uint32_t idx,
+                                          Roller<W>& r) {
+    uint32_t lo = 0, hi = kLdsBlock;   // last descriptor whose prefix is <= idx
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (spre[mid] <= idx) lo = mid; else hi = mid;
+    }
+    uint32_t nxt = spre[lo + 1];
+    r.next = nxt;
+    r.p = sstart[lo] + (int64_t)(idx - spre[lo]);
+    const int64_t last = sstart[lo] + (int64_t)(nxt - spre[lo]) - 1;   // position of the super-mer's last k-mer
+    r.ok = sstart[lo] >= 0 && (uint64_t)last + a.k <= a.n_bytes;
+    if (!r.ok) {
+        set_status(a.status, ST_SPIN);   // a corrupt descriptor must not read out of range
+        return;
+    }
+    extract_kmer<W>(a.packed, r.p, a.k, r.fw, r.rc);
+}
+
+// Shift in base b (code 0..3) at the end of the forward key and its
+// complement at the front of the reverse-complement key.
+template <int W>
+__device__ __forceinline__ void roll_base(uint64_t (&fw)[W], uint64_t (&rc)[W], uint32_t b, uint32_t k) {
+    const uint32_t rb = k - 32u * (W - 1);   // bases in the last word
+    const uint64_t tail_mask = rb == 32 ? ~0ull : ((1ull << (2 * rb)) - 1ull);
+#pragma unroll
+    for (int i = 0; i + 1 < W; i++) {
+        uint64_t top_next = (i + 2 < W) ? (fw[i + 1] >> 62) : (fw[W - 1] >> (2 * rb - 2));
+        fw[i] = (fw[i] << 2) | top_next;
+    }
+    fw[W - 1] = ((fw[W - 1] << 2) | b) & tail_mask;
+    if (W == 1) {
+        rc[0] = (rc[0] >> 2) | ((uint64_t)(3u - b) << (2 * rb - 2));
+    } else {
+        rc[W - 1] = (rc[W - 1] >> 2) | ((rc[W - 2] & 3ull) << (2 * rb - 2));
+#pragma unroll
+        for (int i = W - 2; i >= 1; i--) rc[i] = (rc[i] >> 2) | ((rc[i - 1] & 3ull) << 62);
+        rc[0] = (rc[0] >> 2) | ((uint64_t)(3u - b) << 62);
+    }
+}
+
+// Move the roller to chunk k-mer index idx, the index after the previous one.
+template <int W>
+__device__ __forceinline__ void roll_next(const CountArgs& a, const int64_t* sstart, const uint32_t* spre,
+                                          uint32_t idx, Roller<W>& r) {
+    if (idx >= r.next) {
+        roll_seek<W>(a, sstart, spre, idx, r);
+        return;
+    }
+    r.p += 1;
+    if (!r.ok) return;
+    const int64_t q = r.p + (int64_t)a.k - 1;
+    const uint32_t b = (uint32_t)((a.packed[q >> 5] >> (62 - 2 * (q & 31))) & 3ull);
+    roll_base<W>(r.fw, r.rc, b, a.k);
+}
+
+// Contiguous range of chunk k-mers handled by this thread.
+__device__ __forceinline__ void thread_range(uint32_t total, uint32_t& i0, uint32_t& i1) {
+    const uint32_t m = (total + kLdsBlock - 1) / kLdsBlock;
+    i0 = threadIdx.x * m;
+    i1 = i0 + m < total ? i0 + m : total;
+    if (i0 > total) i0 = total;
+}
+
+// Exclusive prefix of cnt[0..n) into pre[0..n) by the whole block; returns the total.
+__device__ __forceinline__ uint32_t block_scan_array(const uint32_t* cnt, uint32_t* pre, uint32_t n, uint32_t* wsum) {
+    const uint32_t per = (n + kLdsBlock - 1) / kLdsBlock;
+    const uint32_t j0 = threadIdx.x * per;
+    uint32_t sum = 0;
+    for (uint32_t e = 0; e < per; e++)
+        if (j0 + e < n) sum += cnt[j0 + e];
+    uint32_t total;
+    uint32_t run = block_excl_scan(sum, wsum, total);
+    for (uint32_t e = 0; e < per; e++)
+        if (j0 + e < n) {
+            pre[j0 + e] = run;
+            run += cnt[j0 + e];
+        }
+    return total;
+}
+
+// Round size of the scatter stage: R keys per thread, staged in 96 KB of LDS at most.
+template <int W>
+struct ScatterRound { static constexpr int R = W == 1 ? 8 : W == 2 ? 6 : W == 3 ? 4 : W == 4 ? 3 : W == 5 ? 2 : 1; };
+
+// LDS of the chunk stages: descriptor starts, prefixes and scan scratch.
+constexpr uint32_t kChunkHeader = 8 * kLdsBlock + 4 * (kLdsBlock + 4) + 4 * 32;
+
+struct ChunkLds {
+    int64_t* sstart;
+    uint32_t* spre;
+    uint32_t* wsum;
+    uint8_t* rest;
+};
+__device__ __forceinline__ ChunkLds chunk_lds(const Lds& s) {
+    ChunkLds c;
+    c.sstart = (int64_t*)s.u;
+    c.spre = (uint32_t*)(s.u + 8 * kLdsBlock);
+    c.wsum = c.spre + kLdsBlock + 4;
+    c.rest = (uint8_t*)(c.wsum + 32);
+    return c;
+}
+
+// Stage A: keys of this slice per sub-table.
+template <int W>
+__device__ void stage_count(const CountArgs& a, const LdsArgs& l, const Lds& s, uint32_t r, uint32_t chunk) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t b = l.rank_bin[r], v = l.rank_slice[r], V = l.rank_nslice[r], P = l.rank_nsub[r];
+    const ChunkLds c = chunk_lds(s);
+    static_assert(kChunkHeader + 4 * kLdsMaxSub <= kLdsBytes - kLdsReserved, "count stage exceeds the LDS budget");
+    uint32_t* hist = (uint32_t*)c.rest;
+    for (uint32_t j = tid; j < P; j += kLdsBlock) hist[j] = 0;
+    const uint32_t total = load_chunk(a, l, b, chunk, c.sstart, c.spre, c.wsum);
+    uint32_t i0, i1;
+    thread_range(total, i0, i1);
+    Roller<W> ro;
+    for (uint32_t i = i0; i < i1; i++) {
+        if (i == i0) roll_seek<W>(a, c.sstart, c.spre, i, ro);
+        else roll_next<W>(a, c.sstart, c.spre, i, ro);
+        if (!ro.ok) continue;
+        uint64_t key[W];
+        canonical_of<W>(ro.fw, ro.rc, key);
+        const uint64_t h = key_hash<W>(key, a.seed);
+        if (V > 1 && slice_of(h, V) != v) continue;
+        atomicAdd(&hist[sub_of(h, P)], 1u);
+    }
+    __syncthreads();
+    const uint64_t sb = l.rank_spbase[r];
+    for (uint32_t j = tid; j < P; j += kLdsBlock)
+        if (hist[j]) add_dev(&l.sp_cnt[sb + j], hist[j]);
+}
+
+// Stage S: sub-table runs of the rank (one workgroup).
+__device__ void stage_scan(const CountArgs& a, const LdsArgs& l, const Lds& s, uint32_t r) {
+    const uint32_t tid = threadIdx.x, P = l.rank_nsub[r];
+    const uint64_t sb = l.rank_spbase[r];
+    uint64_t* part = (uint64_t*)s.u;
+    const uint32_t per = (P + kLdsBlock - 1) / kLdsBlock;
+    uint64_t sum = 0;
+    for (uint32_t e = 0; e < per; e++) {
+        uint32_t j = tid * per + e;
+        if (j < P) sum += ld_dev(&l.sp_cnt[sb + j]);
+    }
+    part[tid] = sum;
+    __syncthreads();
+    for (uint32_t off = 1; off < kLdsBlock; off <<= 1) {
+        uint64_t y = tid >= off ? part[tid - off] : 0ull;
+        __syncthreads();
+        part[tid] += y;
+        __syncthreads();
+    }
+    uint64_t run = tid ? part[tid - 1] : 0ull;
+    for (uint32_t e = 0; e < per; e++) {
+        uint32_t j = tid * per + e;
+        if (j < P) {
+            st_dev(&l.sp_off[sb + j], run);
+            run += ld_dev(&l.sp_cnt[sb + j]);
+            st_dev(&l.sp_cur[sb + j], 0u);
+        }
+    }
+    if (tid == 0) {
+        st_dev(&l.rank_keys[r], part[kLdsBlock - 1]);
+        if (part[kLdsBlock - 1] > l.slot_keys) set_status(a.status, ST_POOL);
+    }
+}
+
+// Stage C: write the keys of this slice into their sub-table runs. Per round
+// every thread rolls R k-mers; the round's keys are grouped by sub-table in
+// LDS, one global reservation is made per sub-table, and each run is written
+// as consecutive words (coalesced stores).
+template <int W>
+__device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s, uint32_t r, uint32_t chunk) {
+    constexpr int R = ScatterRound<W>::R;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t b = l.rank_bin[r], v = l.rank_slice[r], V = l.rank_nslice[r], P = l.rank_nsub[r];
+    const uint64_t sb = l.rank_spbase[r];
+    uint64_t* slot = l.keys + (uint64_t)(r % l.Q) * l.slot_keys * W;
+    const ChunkLds c = chunk_lds(s);
+    static_assert(kChunkHeader + 3 * 4 * kLdsMaxSub + (uint64_t)R * 8 * W * kLdsBlock <= kLdsBytes - kLdsReserved,
+                  "scatter stage exceeds the LDS budget");
+    uint32_t* cnt = (uint32_t*)c.rest;
+    uint32_t* lp = cnt + kLdsMaxSub;
+    uint32_t* dst = lp + kLdsMaxSub;   // run start of this round, relative to the key slot
+    uint64_t* buf = (uint64_t*)(dst + kLdsMaxSub);
+    for (uint32_t j = tid; j < P; j += kLdsBlock) cnt[j] = 0;
+    const uint32_t total = load_chunk(a, l, b, chunk, c.sstart, c.spre, c.wsum);
+    uint32_t i0, i1;
+    thread_range(total, i0, i1);
+    const uint32_t m = (total + kLdsBlock - 1) / kLdsBlock;
+    const uint32_t rounds = (m + R - 1) / R;
+    Roller<W> ro;
+    for (uint32_t round = 0; round < rounds; round++) {
+        uint64_t key[R][W];
+        uint32_t sp[R], rk[R];
+#pragma unroll
+        for (int e = 0; e < R; e++) {
+            sp[e] = kNone;
+            const uint32_t i = i0 + round * R + e;
+            if (i < i1) {
+                if (i == i0) roll_seek<W>(a, c.sstart, c.spre, i, ro);
+                else roll_next<W>(a, c.sstart, c.spre, i, ro);
+                if (ro.ok) {
+                    canonical_of<W>(ro.fw, ro.rc, key[e]);
+                    const uint64_t h = key_hash<W>(key[e], a.seed);
+                    if (V == 1 || slice_of(h, V) == v) {
+                        sp[e] = sub_of(h, P);
+                        rk[e] = atomicAdd(&cnt[sp[e]], 1u);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        const uint32_t T = block_scan_array(cnt, lp, P, c.wsum);
+        __syncthreads();   // every lp[] written (and every cnt[] read) before keys are placed or counts reset
+        for (uint32_t j = tid; j < P; j += kLdsBlock) {
+            const uint32_t n = cnt[j];
+            if (n) {
+                const uint32_t g = add_dev(&l.sp_cur[sb + j], n);
+                dst[j] = (uint32_t)(ld_dev(&l.sp_off[sb + j]) + g);
+                cnt[j] = 0;
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < R; e++) {
+            if (sp[e] == kNone) continue;
+            const uint32_t pos = lp[sp[e]] + rk[e];
+#pragma unroll
+            for (int w = 0; w < W; w++) buf[(uint64_t)pos * W + w] = key[e][w];
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < T; i += kLdsBlock) {
+            uint32_t lo = 0, hi = P;   // last sub-table whose run starts at or before i
+            while (hi - lo > 1) {
+                uint32_t mid = (lo + hi) >> 1;
+                if (lp[mid] <= i) lo = mid; else hi = mid;
+            }
+            const uint64_t g = (uint64_t)dst[lo] + (i - lp[lo]);
+            if (g < l.slot_keys) {
+#pragma unroll
+                for (int w = 0; w < W; w++) st_dev(&slot[g * W + w], buf[(uint64_t)i * W + w]);
+            } else {
+                set_status(a.status, ST_POOL);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Alg. 1 in an LDS table of C slots (structure of arrays). One probe step per
+// loop iteration, so a lane that waits for a key being published by a lane
+// of its own wave retries only after that lane has finished publishing.
+template <int W>
+__device__ __forceinline__ bool lds_insert(uint64_t* w0, uint64_t* rest, uint32_t* cnt, uint32_t C, uint32_t theta,
+                                           const uint64_t (&key)[W], uint64_t h, uint32_t* status) {
+    if (W > 1 && key[0] == GERBIL_EMPTY) return false;
+    // C is prime and 1 <= step < C: double hashing visits theta distinct slots
+    const uint64_t hh = lds_hash(h);
+    const uint32_t step = 1u + fastrange32((uint32_t)(hh >> 32), C - 1);
+    uint32_t t = 0, spins = 0;
+    uint32_t sl = fastrange32((uint32_t)hh, C);
+    for (;;) {
+        uint64_t cur = __hip_atomic_load(w0 + sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (cur == GERBIL_EMPTY) {
+            uint64_t exp = GERBIL_EMPTY;
+            __hip_atomic_compare_exchange_strong(w0 + sl, &exp, key[0], __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (exp == GERBIL_EMPTY) {
+#pragma unroll
+                for (int i = 1; i < W; i++) rest[(uint32_t)(i - 1) * C + sl] = key[i];
+                if (W > 1) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __hip_atomic_fetch_add(cnt + sl, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                return true;
+            }
+            cur = exp;
+        }
+        if (cur == key[0]) {
+            if (W == 1) {
+                __hip_atomic_fetch_add(cnt + sl, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                return true;
+            }
+            uint32_t c = __hip_atomic_load(cnt + sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (c == 0) {
+                if (++spins > kLdsSpin) {
+                    set_status(status, ST_SPIN);
+                    return true;
+                }
+                continue;   // published in the same iteration by its claimer; look again
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            bool eq = true;
+#pragma unroll
+            for (int i = 1; i < W; i++) eq &= rest[(uint32_t)(i - 1) * C + sl] == key[i];
+            if (eq) {
+                uint32_t old = __hip_atomic_fetch_add(cnt + sl, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (old >= 0xFFFFFFFEu) set_status(status, ST_COUNT_SAT);
+                return true;
+            }
+        }
+        if (++t >= theta) return false;
+        sl += step;
+        if (sl >= C) sl -= C;
+    }
+}
+
+// Keys loaded per thread before they are inserted (independent loads in flight).
+template <int W>
+struct TableBatch { static constexpr int K = W <= 2 ? 8 : W <= 4 ? 4 : W == 5 ? 2 : 1; };
+
+// Stage D: count one sub-table in LDS, then dump it.
+template <int W>
+__device__ void stage_table(const CountArgs& a, const LdsArgs& l, const Lds& s, uint32_t r, uint32_t j,
+                            uint32_t& wmax) {
+    constexpr int K = TableBatch<W>::K;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t C = l.table_slots;
+    uint64_t* w0 = (uint64_t*)s.u;
+    uint64_t* rest = w0 + C;
+    uint32_t* cnt = (uint32_t*)(rest + (uint64_t)(W - 1) * C);
+    uint32_t* wsum = cnt + C + 1;
+    uint64_t* s_base = (uint64_t*)(((uintptr_t)(wsum + 32) + 7) & ~(uintptr_t)7);
+    const uint64_t sb = l.rank_spbase[r];
+    const uint64_t n = ld_dev(&l.sp_cnt[sb + j]);
+    const uint64_t off = ld_dev(&l.sp_off[sb + j]);
+    const uint64_t* keys = l.keys + (uint64_t)(r % l.Q) * l.slot_keys * W + off * W;
+    for (uint32_t i = tid; i < C; i += kLdsBlock) {
+        w0[i] = GERBIL_EMPTY;
+        cnt[i] = 0;
+    }
+    __syncthreads();
+    const uint64_t lim = (off + n <= l.slot_keys) ? n : 0;   // a run past the slot was never written
+    for (uint64_t base = 0; base < lim; base += (uint64_t)kLdsBlock * K) {
+        uint64_t key[K][W];
+#pragma unroll
+        for (int e = 0; e < K; e++) {
+            const uint64_t i = base + (uint64_t)e * kLdsBlock + tid;
+            if (i < lim) {
+#pragma unroll
+                for (int w = 0; w < W; w++) key[e][w] = ld_dev(&keys[i * W + w]);
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < K; e++) {
+            const uint64_t i = base + (uint64_t)e * kLdsBlock + tid;
+            if (i < lim) {
+                const uint64_t h = key_hash<W>(key[e], a.seed);
+                if (!lds_insert<W>(w0, rest, cnt, C, l.theta, key[e], h, a.status)) overflow_push<W>(a, key[e]);
+            }
+        }
+    }
+    __syncthreads();
+    // dump: count this thread's pairs, one reservation for the block, write
+    uint32_t mine = 0;
+    for (uint32_t sl = tid; sl < C; sl += kLdsBlock) {
+        const uint32_t c = cnt[sl];
+        if (c) {
+            if (c < kLdsHist) atomicAdd(&s.hist[c], 1u);
+            else add_dev(&a.hist[c < kHistInternal - 1 ? c : kHistInternal - 1], 1ull);
+            wmax = c > wmax ? c : wmax;
+            mine += c >= a.threshold;
+        }
+    }
+    uint32_t total;
+    const uint32_t pre = block_excl_scan(mine, wsum, total);
+    if (tid == 0) *s_base = total ? add_dev(a.n_out, (uint64_t)total) : 0ull;
+    __syncthreads();
+    uint64_t pos = *s_base + pre;
+    for (uint32_t sl = tid; sl < C && mine; sl += kLdsBlock) {
+        const uint32_t c = cnt[sl];
+        if (c && c >= a.threshold) {
+            if (pos < a.cap) {
+                a.out_keys[pos * W] = w0[sl];
+#pragma unroll
+                for (int i = 1; i < W; i++) a.out_keys[pos * W + i] = rest[(uint32_t)(i - 1) * C + sl];
+                a.out_counts[pos] = c;
+            } else {
+                set_status(a.status, ST_OUT_CAP);
+            }
+            pos++;
+            mine--;
+        }
+    }
+}
+
+template <int W>
+__device__ __forceinline__ void run_stage(const CountArgs& a, const LdsArgs& l, const Lds& s, uint32_t st,
+                                          uint32_t r, uint32_t local, uint32_t& wmax) {
+    switch (st) {
+        case 0: stage_count<W>(a, l, s, r, local); break;
+        case 1: stage_scan(a, l, s, r); break;
+        case 2: stage_scatter<W>(a, l, s, r, local); break;
+        default: stage_table<W>(a, l, s, r, local, wmax); break;
+    }
+}
+
+__device__ __forceinline__ void hist_begin(const Lds& s) {
+    for (uint32_t b = threadIdx.x; b < kLdsHist; b += kLdsBlock) s.hist[b] = 0;
+    __syncthreads();
+}
+__device__ __forceinline__ void hist_end(const CountArgs& a, const Lds& s, uint32_t wmax) {
+    flush_max(a.max_count, wmax);
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < kLdsHist; b += kLdsBlock)
+        if (s.hist[b]) add_dev(&a.hist[b], (uint64_t)s.hist[b]);
+}
+
+// BATCHED: every stage of every rank from one queue.
+template <int W>
+__global__ void __launch_bounds__(kLdsBlock) k_lds_persistent(CountArgs a, LdsArgs l) {
+    extern __shared__ __align__(16) uint8_t lds_raw[];
+    const Lds s = lds_carve(lds_raw);
+    uint64_t* s_item = (uint64_t*)(lds_raw + kLdsHist * 4);
+    uint32_t* s_seg = (uint32_t*)(s_item + 1);
+    const uint32_t tid = threadIdx.x;
+    if (tid == 0) *s_seg = 0;
+    hist_begin(s);
+    uint32_t wmax = 0;
+    const uint32_t ns = *l.n_seg;
+    const uint64_t total = l.seg_start[ns];
+    const uint32_t L = l.lag;
+    for (;;) {
+        if (tid == 0) {
+            uint64_t item = add_dev(l.cursor, 1ull);
+            *s_item = item;
+            if (item < total) *s_seg = find_segment(l.seg_start, ns, item, *s_seg);
+        }
+        __syncthreads();
+        const uint64_t item = *s_item;
+        if (item >= total) break;
+        const uint32_t seg = *s_seg;
+        const uint32_t st = seg & 3, tick = seg >> 2;
+        const uint32_t lagv = st == 0 ? 0u : st == 1 ? 1u : st == 2 ? 2u : 2u + L;
+        const uint32_t r = tick - lagv;
+        const uint32_t local = (uint32_t)(item - l.seg_start[seg]);
+        if (tid == 0) {
+            if (st == 1) wait_done(l.done + 4 * r + 0, l.rank_nchunk[r], kLdsWait, a.status, ST_SPIN);
+            if (st == 2) {
+                wait_done(l.done + 4 * r + 1, 1u, kLdsWait, a.status, ST_SPIN);
+                if (r >= l.Q) wait_done(l.done + 4 * (r - l.Q) + 3, l.rank_nsub[r - l.Q], kLdsWait, a.status, ST_SPIN);
+            }
+            if (st == 3) wait_done(l.done + 4 * r + 2, l.rank_nchunk[r], kLdsWait, a.status, ST_SPIN);
+        }
+        __syncthreads();
+        run_stage<W>(a, l, s, st, r, local, wmax);
+        signal_done(l.done + 4 * r + st);
+        __syncthreads();
+    }
+    hist_end(a, s, wmax);
+}
+
+// PLAIN: `items` blocks of one stage of one rank.
+template <int W>
+__global__ void __launch_bounds__(kLdsBlock) k_lds_stage(CountArgs a, LdsArgs l, uint32_t st, uint32_t r) {
+    extern __shared__ __align__(16) uint8_t lds_raw[];
+    const Lds s = lds_carve(lds_raw);
+    hist_begin(s);
+    uint32_t wmax = 0;
+    run_stage<W>(a, l, s, st, r, blockIdx.x, wmax);
+    __syncthreads();
+    hist_end(a, s, wmax);
+}
+
+template <int W>
+static hipError_t persistent_lds_w(const CountArgs& a, const LdsArgs& l, uint32_t grid, hipStream_t s) {
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_lds_persistent<W>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL(k_lds_persistent<W>, dim3(grid), dim3(kLdsBlock), kLdsBytes, s, a, l);
+    return hipGetLastError();
+}
+
+template <int W>
+static hipError_t stage_lds_w(const CountArgs& a, const LdsArgs& l, uint32_t st, uint32_t r, uint32_t items,
+                              hipStream_t s) {
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_lds_stage<W>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           kLdsBytes);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    if (items == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lds_stage<W>, dim3(items), dim3(kLdsBlock), kLdsBytes, s, a, l, st, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_lds_persistent(const CountArgs& a, const LdsArgs& l, uint32_t grid, hipStream_t s) {
+    switch (a.W) {
+        case 1: return persistent_lds_w<1>(a, l, grid, s);
+        case 2: return persistent_lds_w<2>(a, l, grid, s);
+        case 3: return persistent_lds_w<3>(a, l, grid, s);
+        case 4: return persistent_lds_w<4>(a, l, grid, s);
+        case 5: return persistent_lds_w<5>(a, l, grid, s);
+        case 6: return persistent_lds_w<6>(a, l, grid, s);
+        case 7: return persistent_lds_w<7>(a, l, grid, s);
+        case 8: return persistent_lds_w<8>(a, l, grid, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_lds_stage(const CountArgs& a, const LdsArgs& l, uint32_t st, uint32_t r, uint32_t items,
+                            hipStream_t s) {
+    switch (a.W) {
+        case 1: return stage_lds_w<1>(a, l, st, r, items, s);
+        case 2: return stage_lds_w<2>(a, l, st, r, items, s);
+        case 3: return stage_lds_w<3>(a, l, st, r, items, s);
+        case 4: return stage_lds_w<4>(a, l, st, r, items, s);
+        case 5: return stage_lds_w<5>(a, l, st, r, items, s);
+        case 6: return stage_lds_w<6>(a, l, st, r, items, s);
+        case 7: return stage_lds_w<7>(a, l, st, r, items, s);
+        case 8: return stage_lds_w<8>(a, l, st, r, items, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace gerbil

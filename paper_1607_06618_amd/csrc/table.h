@@ -13,7 +13,8 @@
 //     each key) of a bucket are one 64-byte line, loaded by one lane at once,
 //     so a probe scans 8 candidates whatever k is (probe words are stored
 //     apart from the rest of the key, structure of arrays);
-//   * trial t probes bucket fastrange(h1 + t*h2) with h2 odd (double hashing);
+//   * trial t probes bucket (b0 + t*s) mod nb with nb a power of two and s odd
+//     (double hashing with a full period);
 //   * a slot is claimed by CAS on word 0 (EMPTY = all ones: a canonical key
 //     never has word 0 = all ones when k < 64; for k >= 64 such keys take the
 //     emergency path). For W >= 2 the claimer then stores words 1..W-1 and
@@ -35,26 +36,17 @@ namespace gerbil {
 
 constexpr uint32_t kSpinLimit = 1u << 22;   // bounded wait for an unpublished slot
 
-// Publication of words 1..W-1 before the counter.
-#ifndef GERBIL_ORDERED_PUBLISH
-#define GERBIL_ORDERED_PUBLISH 0
-#endif
-#if GERBIL_ORDERED_PUBLISH
-// Experimental: words 1..W-1 are written with device-coherent stores and the
-// counter is raised only after every store has been acknowledged.
+// Publication of words 1..W-1 before the counter. Every word a workgroup
+// shares with another one is accessed with device-coherent (agent-scope
+// atomic) loads and stores, which keep each location coherent across all
+// CUs and XCDs. The claimer drains its stores (s_waitcnt vmcnt(0): each has
+// been performed) before it raises the counter; a reader loads the other
+// words only after it has seen a non-zero counter. No cache write-back or
+// invalidation is needed on the hot path.
 __device__ __forceinline__ void store_rest(uint64_t* p, uint64_t v) { st_dev(p, v); }
 __device__ __forceinline__ uint64_t load_rest(const uint64_t* p) { return ld_dev(p); }
-__device__ __forceinline__ void publish_fence() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+__device__ __forceinline__ void publish_fence() { drain_memory(); }
 __device__ __forceinline__ void acquire_fence() { asm volatile("" ::: "memory"); }
-#else
-// The release fence makes the stores of the other words visible at agent
-// scope before the counter increment; the reader acquires once it has seen a
-// non-zero counter.
-__device__ __forceinline__ void store_rest(uint64_t* p, uint64_t v) { *p = v; }
-__device__ __forceinline__ uint64_t load_rest(const uint64_t* p) { return *p; }
-__device__ __forceinline__ void publish_fence() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
-__device__ __forceinline__ void acquire_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
-#endif
 
 template <int W>
 __device__ __forceinline__ void overflow_push(const CountArgs& a, const uint64_t (&key)[W]) {
@@ -73,9 +65,12 @@ template <int W>
 __device__ __forceinline__ bool table_insert(const CountArgs& a, const Table& t, uint32_t nb,
                                              const uint64_t (&key)[W], uint64_t h) {
     if (W > 1 && key[0] == GERBIL_EMPTY) return false;
-    const uint32_t h1 = (uint32_t)h, h2 = (uint32_t)(h >> 32) | 1u;
-    for (uint32_t trial = 0; trial < a.theta; trial++) {
-        const uint64_t bucket = fastrange32(h1 + trial * h2, nb);
+    // nb is a power of two and the step is odd: the theta buckets are distinct
+    const uint32_t mask = nb - 1;
+    const uint32_t step = ((uint32_t)(h >> 32) | 1u) & mask | 1u;
+    uint32_t bk = fastrange32((uint32_t)h, nb);
+    for (uint32_t trial = 0; trial < a.theta; trial++, bk = (bk + step) & mask) {
+        const uint64_t bucket = bk;
         uint64_t* w0 = t.w0 + bucket * kBucket;
         uint32_t match = 0, empty = 0;
 #pragma unroll
@@ -178,7 +173,7 @@ __device__ __forceinline__ void compact_slot(const CountArgs& a, const Table& t,
         if (pos < a.cap) {
             a.out_keys[pos * W] = ld_dev(t.w0 + slot);
 #pragma unroll
-            for (int i = 1; i < W; i++) a.out_keys[pos * W + i] = t.rest[(uint64_t)(i - 1) * t.stride + slot];
+            for (int i = 1; i < W; i++) a.out_keys[pos * W + i] = load_rest(t.rest + (uint64_t)(i - 1) * t.stride + slot);
             a.out_counts[pos] = c;
         } else {
             set_status(a.status, ST_OUT_CAP);

@@ -105,7 +105,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gerbil_encode.argtypes = [vp, vp, u64, u64, u32, vp, u64, P(gerbil_encoded), vp]
     lib.gerbil_bin_workspace.argtypes = [P(gerbil_encoded), P(gerbil_params), P(u64)]
     lib.gerbil_bin.argtypes = [P(gerbil_encoded), P(gerbil_params), vp, u64, P(gerbil_bins), vp]
-    lib.gerbil_count_workspace.argtypes = [P(gerbil_bins), P(gerbil_params), P(u64)]
+    lib.gerbil_count_workspace.argtypes = [P(gerbil_bins), P(gerbil_params), P(u64), vp]
     lib.gerbil_count.argtypes = [P(gerbil_bins), P(gerbil_params), vp, u64, vp, vp, u64, P(gerbil_counted), vp]
     lib.gerbil_histogram.argtypes = [P(gerbil_counted), vp, u32, vp]
     lib.gerbil_result.argtypes = [P(gerbil_encoded), P(gerbil_bins), P(gerbil_counted), P(gerbil_report), vp]
@@ -156,9 +156,9 @@ def gerbil_bin(enc: gerbil_encoded, p: gerbil_params, ws_ptr: int, ws_bytes: int
     return load().gerbil_bin(ctypes.byref(enc), ctypes.byref(p), ws_ptr, ws_bytes, ctypes.byref(out), stream)
 
 
-def gerbil_count_workspace(bins: gerbil_bins, p: gerbil_params) -> int:
+def gerbil_count_workspace(bins: gerbil_bins, p: gerbil_params, stream: int = 0) -> int:
     out = u64(0)
-    st = load().gerbil_count_workspace(ctypes.byref(bins), ctypes.byref(p), ctypes.byref(out))
+    st = load().gerbil_count_workspace(ctypes.byref(bins), ctypes.byref(p), ctypes.byref(out), stream)
     if st:
         raise GerbilError("gerbil_count_workspace", st)
     return out.value
@@ -275,8 +275,8 @@ class Job:
         """Size the count workspace and output arrays (synchronises once)."""
         torch = self.torch
         if self.ws_count is None:
-            self.ws_count = torch.empty(gerbil_count_workspace(self.bins, self.p), dtype=torch.uint8,
-                                        device=self.ascii_d.device)
+            self.ws_count = torch.empty(gerbil_count_workspace(self.bins, self.p, _stream_handle(self.stream)),
+                                        dtype=torch.uint8, device=self.ascii_d.device)
         if self.keys_d is None:
             if self.cap is None:
                 if n_valid is None:

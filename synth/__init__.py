@@ -118,6 +118,22 @@ class Workload:
             max(1, int(self.n_reads * factor))
         return replace(self, name=name or f"{self.name}@{factor:g}", G=G, n_reads=n)
 
+    def bin_map(self) -> Optional[np.ndarray]:
+        """Seeded minimizer -> bin map for the skewed-bins workload, else None.
+
+        Bin weights are LogNormal(0, 0.97) (over 1024 bins the expected
+        max/median weight is about 20); every m-mer code is given to a bin
+        with probability proportional to its weight, so bin sizes follow the
+        weights. Only the m-mer code space is used here, no m-mer arithmetic.
+        """
+        if not self.skew_bins:
+            return None
+        rng = np.random.default_rng(self.seed)
+        nb, n_codes = self.n_bins, 4 ** self.m
+        weights = np.exp(rng.normal(0.0, 0.97, nb))
+        cdf = np.cumsum(weights / weights.sum())
+        return np.searchsorted(cdf, rng.random(n_codes), side="right").clip(0, nb - 1).astype(np.uint32)
+
     def generate(self, threads: Optional[int] = None):
         """(ascii, offsets) for this workload."""
         g = genome(self.G, self.gc, self.rep_frac, 0.02, self.seed)

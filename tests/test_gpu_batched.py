@@ -14,6 +14,7 @@ from paper_1607_06618_amd import gerbil as g
 pytestmark = pytest.mark.gpu
 
 B = g.GERBIL_BATCHED
+TABLES = [pytest.param(g.GERBIL_TABLE_LDS, id="lds"), pytest.param(g.GERBIL_TABLE_HBM, id="hbm")]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -33,36 +34,41 @@ def same_as_oracle(res, ref, hist_len):
     assert np.array_equal(res.hist, ref.folded_hist(hist_len))
 
 
-def test_batched_c1_full():
+@pytest.mark.parametrize("table", TABLES)
+def test_batched_c1_full(table):
     w = synth.CONFIGS["c1_tiny"]
     a, o = w.generate()
     ref = oracle.count(a, o, w.k, threshold=w.threshold)
-    res = g.count_kmers(a, o, w.k, w.m, w.n_bins, w.threshold, 512, mode=B)
+    res = g.count_kmers(a, o, w.k, w.m, w.n_bins, w.threshold, 512, mode=B, table=table)
     same_as_oracle(res, ref, 512)
     assert res.report.n_overflow == 0
 
 
 @pytest.mark.parametrize("name,scale", [("c2_k65", 0.01), ("c3_skew", 0.001), ("c4_longk", 0.002)])
-def test_batched_config_shapes(name, scale):
+@pytest.mark.parametrize("table", TABLES)
+def test_batched_config_shapes(name, scale, table):
     w = synth.CONFIGS[name].scaled(scale)
     a, o = w.generate()
     ref = oracle.count(a, o, w.k, threshold=w.threshold)
-    res = g.count_kmers(a, o, w.k, w.m, w.n_bins, w.threshold, 1024, mode=B)
+    res = g.count_kmers(a, o, w.k, w.m, w.n_bins, w.threshold, 1024, mode=B, table=table)
     same_as_oracle(res, ref, 1024)
 
 
 @pytest.mark.parametrize("pool,load,theta", [(1, 0.5, 8), (2, 0.5, 8), (3, 0.7, 4), (8, 0.3, 8), (64, 0.9, 2),
                                              (1, 0.95, 1)])
-def test_batched_schedule_parameters(pool, load, theta):
+@pytest.mark.parametrize("table", TABLES)
+def test_batched_schedule_parameters(pool, load, theta, table):
     w = synth.CONFIGS["c2_k65"].scaled(0.003)
     a, o = w.generate()
     ref = oracle.count(a, o, w.k, threshold=w.threshold)
-    res = g.count_kmers(a, o, w.k, w.m, 64, w.threshold, 256, mode=B, pool=pool, load_factor=load, max_probes=theta)
+    res = g.count_kmers(a, o, w.k, w.m, 64, w.threshold, 256, mode=B, pool=pool, load_factor=load, max_probes=theta,
+                        table=table)
     same_as_oracle(res, ref, 256)
 
 
 @pytest.mark.parametrize("k", [16, 32, 33, 64, 99, 160, 256])
-def test_batched_random_k(k):
+@pytest.mark.parametrize("table", TABLES)
+def test_batched_random_k(k, table):
     rng = np.random.default_rng(77 + k)
     gen = "".join(np.array(list("ACGT"))[rng.integers(0, 4, 4000)].tolist())
     reads = []
@@ -73,15 +79,16 @@ def test_batched_random_k(k):
     reads += random_reads(rng, 50, 0, 400)
     a, o = reads_to_csr(reads)
     ref = oracle.count(a, o, k, threshold=2)
-    res = g.count_kmers(a, o, k, min(9, k - 1), 97, 2, 128, mode=B)
+    res = g.count_kmers(a, o, k, min(9, k - 1), 97, 2, 128, mode=B, table=table)
     same_as_oracle(res, ref, 128)
 
 
-def test_batched_repeated_runs_reuse_workspace():
+@pytest.mark.parametrize("table", TABLES)
+def test_batched_repeated_runs_reuse_workspace(table):
     w = synth.CONFIGS["c1_tiny"].scaled(0.2)
     a, o = w.generate()
     ad, od = to_device(a, o)
-    p = g.make_params(w.k, w.m, w.n_bins, w.threshold, mode=B, pool=3)
+    p = g.make_params(w.k, w.m, w.n_bins, w.threshold, mode=B, pool=3, table=table)
     job = g.Job(ad, od, a.size, p, hist_len=128)
     ref = oracle.count(a, o, w.k, threshold=w.threshold)
     for _ in range(4):
@@ -89,7 +96,8 @@ def test_batched_repeated_runs_reuse_workspace():
         same_as_oracle(job.result(), ref, 128)
 
 
-def test_batched_and_plain_agree_on_skewed_bins():
+@pytest.mark.parametrize("table", TABLES)
+def test_batched_and_plain_agree_on_skewed_bins(table):
     w = synth.CONFIGS["c3_skew"].scaled(0.002)
     a, o = w.generate()
     rng = np.random.default_rng(5)
@@ -98,8 +106,10 @@ def test_batched_and_plain_agree_on_skewed_bins():
     bmap[rng.random(4 ** w.m) < 0.5] = 0
     import torch
     bm = torch.from_numpy(bmap.view(np.int32)).cuda()
-    r1 = g.count_kmers(a, o, w.k, w.m, w.n_bins, w.threshold, 256, mode=B, bin_map_ptr=bm.data_ptr())
-    r0 = g.count_kmers(a, o, w.k, w.m, w.n_bins, w.threshold, 256, mode=g.GERBIL_PLAIN, bin_map_ptr=bm.data_ptr())
+    r1 = g.count_kmers(a, o, w.k, w.m, w.n_bins, w.threshold, 256, mode=B, bin_map_ptr=bm.data_ptr(),
+                       table=table)
+    r0 = g.count_kmers(a, o, w.k, w.m, w.n_bins, w.threshold, 256, mode=g.GERBIL_PLAIN,
+                       bin_map_ptr=bm.data_ptr(), table=table)
     k1, c1 = r1.sorted()
     k0, c0 = r0.sorted()
     assert np.array_equal(k1, k0) and np.array_equal(c1, c0) and np.array_equal(r1.hist, r0.hist)

@@ -15,6 +15,8 @@ from paper_1607_06618_amd import gerbil as g
 
 pytestmark = pytest.mark.gpu
 
+TABLES = [pytest.param(g.GERBIL_TABLE_LDS, id="lds"), pytest.param(g.GERBIL_TABLE_HBM, id="hbm")]
+
 
 @pytest.fixture(scope="module", autouse=True)
 def _need_gpu():
@@ -159,7 +161,8 @@ def test_fig1_supermers_on_gpu(order):
 
 @pytest.mark.parametrize("k,t", [(2, 1), (5, 1), (16, 2), (31, 1), (32, 2), (33, 1), (55, 2), (63, 1), (64, 2),
                                  (65, 2), (96, 1), (99, 3), (128, 2), (160, 1), (200, 2), (256, 1)])
-def test_count_parity_random(k, t):
+@pytest.mark.parametrize("table", TABLES)
+def test_count_parity_random(k, t, table):
     rng = np.random.default_rng(1000 + k)
     # a small genome sampled with errors gives repeated k-mers at every k
     gen = "".join(np.array(list("ACGT"))[rng.integers(0, 4, 3000)].tolist())
@@ -175,44 +178,50 @@ def test_count_parity_random(k, t):
     reads += random_reads(rng, 30, 0, 300)
     a, o = reads_to_csr(reads)
     m = min(9, k - 1)
-    run_and_compare(a, o, k, m, 37, t, hist_len=64)
+    run_and_compare(a, o, k, m, 37, t, hist_len=64, table=table)
 
 
-def test_count_parity_c1_full():
+@pytest.mark.parametrize("table", TABLES)
+def test_count_parity_c1_full(table):
     w = synth.CONFIGS["c1_tiny"]
     a, o = w.generate()
-    res, ref = run_and_compare(a, o, w.k, w.m, w.n_bins, w.threshold, hist_len=512, expect_overflow=False)
+    res, ref = run_and_compare(a, o, w.k, w.m, w.n_bins, w.threshold, hist_len=512, expect_overflow=False,
+                               table=table)
     assert ref.n_valid > 6_000_000
 
 
 @pytest.mark.parametrize("name,scale", [("c2_k65", 0.01), ("c3_skew", 0.001), ("c4_longk", 0.002)])
-def test_count_parity_config_shapes(name, scale):
+@pytest.mark.parametrize("table", TABLES)
+def test_count_parity_config_shapes(name, scale, table):
     w = synth.CONFIGS[name].scaled(scale)
     a, o = w.generate()
-    run_and_compare(a, o, w.k, w.m, w.n_bins, w.threshold, hist_len=1024)
+    run_and_compare(a, o, w.k, w.m, w.n_bins, w.threshold, hist_len=1024, table=table)
 
 
 @pytest.mark.parametrize("k", [31, 65, 99])
-def test_overflow_path_is_exact(k):
+@pytest.mark.parametrize("table", TABLES)
+def test_overflow_path_is_exact(k, table):
     w = synth.CONFIGS["c1_tiny"].scaled(0.05)
     a, o = w.generate()
-    run_and_compare(a, o, k, 9, 8, 1, max_probes=1, load_factor=0.95, expect_overflow=True)
+    run_and_compare(a, o, k, 9, 8, 1, max_probes=1, load_factor=0.95, expect_overflow=True, table=table)
 
 
-def test_keys_with_all_t_first_word_take_the_emergency_path():
+@pytest.mark.parametrize("table", TABLES)
+def test_keys_with_all_t_first_word_take_the_emergency_path(table):
     k = 65
     reads = ["T" * 32 + "A" * 40, "T" * 33 + "A" * 33 + "C", "GG" + "T" * 32 + "A" * 35] * 20
     reads += ["ACGTTGCA" * 30] * 5
     a, o = reads_to_csr(reads)
-    run_and_compare(a, o, k, 9, 4, 1, expect_overflow=True)
+    run_and_compare(a, o, k, 9, 4, 1, expect_overflow=True, table=table)
 
 
-def test_single_key_contention():
+@pytest.mark.parametrize("table", TABLES)
+def test_single_key_contention(table):
     L = 260
     reads = ["A" * L] * 3000 + ["T" * L] * 3000
     a, o = reads_to_csr(reads)
     for k in (32, 65, 200):
-        res, ref = run_and_compare(a, o, k, 9, 16, 2)
+        res, ref = run_and_compare(a, o, k, 9, 16, 2, table=table)
         assert res.counts.tolist() == [6000 * (L - k + 1)]
 
 
@@ -257,13 +266,34 @@ def test_superm_capacity_error():
 
 
 @pytest.mark.parametrize("load,theta,block", [(0.25, 8, 64), (0.9, 2, 1024), (0.5, 32, 512)])
-def test_results_do_not_depend_on_table_parameters(load, theta, block):
+@pytest.mark.parametrize("table", TABLES)
+def test_results_do_not_depend_on_table_parameters(load, theta, block, table):
     w = synth.CONFIGS["c1_tiny"].scaled(0.2)
     a, o = w.generate()
-    run_and_compare(a, o, 33, 7, 64, 2, load_factor=load, max_probes=theta, block=block)
+    run_and_compare(a, o, 33, 7, 64, 2, load_factor=load, max_probes=theta, block=block, table=table)
 
 
 def test_empty_and_short_input():
     a, o = reads_to_csr(["ACG", "", "NNNNNNNNNN"])
     res = g.count_kmers(a, o, 8, 3, 4, 1)
     assert res.keys.shape[0] == 0 and res.report.n_valid == 0 and int(res.hist.sum()) == 0
+
+
+# ------------------------------------------------------- LDS sub-tables
+
+@pytest.mark.parametrize("mode", [g.GERBIL_PLAIN, g.GERBIL_BATCHED])
+def test_lds_large_bin_is_sliced(mode):
+    """One bin of 6.8M k-mers with 64-key sub-tables: the bin is cut into hash
+    slices (16384 sub-tables per slice at most)."""
+    w = synth.CONFIGS["c1_tiny"]
+    a, o = w.generate()
+    run_and_compare(a, o, w.k, w.m, 1, w.threshold, hist_len=512, table=g.GERBIL_TABLE_LDS, mode=mode,
+                    load_factor=0.011)
+
+
+@pytest.mark.parametrize("pool", [1, 2, 5, 64])
+def test_lds_key_slots(pool):
+    w = synth.CONFIGS["c2_k65"].scaled(0.003)
+    a, o = w.generate()
+    run_and_compare(a, o, w.k, w.m, 64, w.threshold, hist_len=256, table=g.GERBIL_TABLE_LDS,
+                    mode=g.GERBIL_BATCHED, pool=pool)
