@@ -40,6 +40,7 @@ def parse_args(argv=None):
     ap.add_argument("--table", default="lds", choices=["lds", "hbm"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--stage-clocks", action="store_true", help="report busy time per LDS stage (batched)")
     return ap.parse_args(argv)
 
 
@@ -147,6 +148,10 @@ def main(argv=None):
         p = g.make_params(w.k, w.m, w.n_bins, w.threshold, mode=mode, pool=args.pool, load_factor=args.load, table=table,
                           bin_map_ptr=bin_map_d.data_ptr() if bin_map_d is not None else 0,
                           timing_events=ctypes.addressof(ev))
+        clocks_d = None
+        if args.stage_clocks and mode == g.GERBIL_BATCHED:
+            clocks_d = torch.zeros(8, dtype=torch.int64, device=dev)
+            p.stage_clocks = clocks_d.data_ptr()
         job = g.Job(ascii_d, offsets_d, int(offsets[-1]), p, hist_len=65536)
         # first pass sizes the workspaces (synchronises); outputs are shared between schedules
         job.encode()
@@ -178,6 +183,15 @@ def main(argv=None):
         kms = sum(kms_all) / len(kms_all)
         res_t = job.result()
         results[mode_name] = dict(job=job, res=res_t, wall=wall, step_ms=step_ms, kernel_ms=kms, ev=ev)
+        if clocks_d is not None:
+            c = clocks_d.cpu().numpy()
+            runs = args.warmup + args.steps
+            names = ["count", "scan", "scatter", "table"]
+            results[mode_name]["stage_ms"] = {names[i]: float(c[i]) / 1e5 / runs for i in range(4)}
+            results[mode_name]["stage_items"] = {names[i]: int(c[4 + i]) // runs for i in range(4)}
+            print(f"[bench] {mode_name} stage busy ms (summed over workgroups, per step): "
+                  f"{results[mode_name]['stage_ms']} items {results[mode_name]['stage_items']}",
+                  file=sys.stderr, flush=True)
         print(f"[bench] {mode_name}: {args.steps} steps in {wall:.3f} s, step p50 {percentile(step_ms, 50):.2f} ms, "
               f"counting kernel {kms:.2f} ms", file=sys.stderr, flush=True)
 
@@ -233,6 +247,9 @@ def main(argv=None):
         out[f"{m}_kmers_per_s"] = n_valid * args.steps / r["wall"]
         out[f"{m}_ms_per_step"] = 1000.0 * r["wall"] / args.steps
         out[f"{m}_count_kernel_ms"] = r["kernel_ms"]
+        if "stage_ms" in r:
+            out[f"{m}_stage_busy_ms"] = r["stage_ms"]
+            out[f"{m}_stage_items"] = r["stage_items"]
     if "batched" in results and "plain" in results:
         out["batched_over_plain"] = results["plain"]["wall"] / results["batched"]["wall"]
     print(json.dumps(out), flush=True)

@@ -104,6 +104,10 @@ typedef struct {
     hipEvent_t* timing_events; /* optional hipEvent_t[2] recorded on the stream just before and just
                                   after the main counting kernel(s): the persistent kernel (BATCHED)
                                   or the per-bin insert and dump launches (PLAIN); NULL = none      */
+    uint64_t* stage_clocks;  /* optional device uint64[8], zeroed by the caller: busy time (in
+                                units of the 100 MHz wall clock) of the four LDS stages (count,
+                                scan, scatter, table) in [0..3] and their item counts in [4..7];
+                                NULL = none                                                       */
 } gerbil_params;
 
 /* Output of gerbil_encode. All pointers point into the encode workspace. */

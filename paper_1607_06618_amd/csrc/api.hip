@@ -360,6 +360,7 @@ int32_t count_lds(const gerbil_bins* bins, const gerbil_params* p, void* ws, uin
     l.target = z.target;
     l.table_slots = z.C;
     l.theta = p->max_probes ? p->max_probes : kDefaultLdsTheta;
+    l.stage_clocks = p->stage_clocks;
     l.bin_off = bins->bin_off;
     l.bin_kmers = bins->bin_kmers;
     l.done = LL.done;

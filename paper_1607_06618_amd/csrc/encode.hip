@@ -131,9 +131,11 @@ hipError_t launch_pack(const uint8_t* ascii, uint64_t n_bytes, uint64_t* packed,
     return hipGetLastError();
 }
 
-// Words of the bitmaps beyond the end read as zero.
+// Words of the bitmaps at or beyond the end read as zero: both bitmaps have a
+// zero word at index n, so the index is clamped instead of branching (all
+// loads of a thread can then be in flight together).
 __device__ __forceinline__ uint64_t ld_or_zero(const uint64_t* __restrict__ a, uint64_t i, uint64_t n) {
-    return i < n ? a[i] : 0ull;
+    return a[i < n ? i : n];
 }
 
 constexpr int kOkWords = 6;  // 64 output bits + up to 255 following bits, plus one word for funnel shifts

@@ -154,6 +154,7 @@ struct LdsArgs {
     uint32_t target;          // keys per sub-table
     uint32_t table_slots;     // LDS slots per sub-table
     uint32_t theta;           // probes per key before the emergency area
+    uint64_t* stage_clocks;   // optional [8]: busy wall-clock ticks per stage, then items per stage
     const uint64_t* bin_off;
     const uint64_t* bin_kmers;
     uint32_t* done;           // [4 * ranks_cap] finished items per (rank, stage)

@@ -250,6 +250,8 @@ struct Roller {
     int64_t p;        // position of the current k-mer
     uint32_t next;    // chunk k-mer index at which the next super-mer starts
     bool ok;          // the super-mer lies inside the reads
+    int64_t q;        // packed word holding the next base to shift in
+    uint64_t cur, nxt;   // packed words q and q+1 (nxt is fetched 32 bases before it is used)
 };
 
 template <int W>
@@ -270,6 +272,9 @@ __device__ __forceinline__ void roll_seek(const CountArgs& a, const int64_t* sst
         return;
     }
     extract_kmer<W>(a.packed, r.p, a.k, r.fw, r.rc);
+    r.q = (r.p + (int64_t)a.k) >> 5;   // next base: position p + k (< n_bytes + 1, so q + 1 is a padded word)
+    r.cur = a.packed[r.q];
+    r.nxt = a.packed[r.q + 1];
 }
 
 // Shift in base b (code 0..3) at the end of the forward key and its
@@ -304,8 +309,13 @@ __device__ __forceinline__ void roll_next(const CountArgs& a, const int64_t* sst
     }
     r.p += 1;
     if (!r.ok) return;
-    const int64_t q = r.p + (int64_t)a.k - 1;
-    const uint32_t b = (uint32_t)((a.packed[q >> 5] >> (62 - 2 * (q & 31))) & 3ull);
+    const int64_t x = r.p + (int64_t)a.k - 1;   // the base that enters the window
+    if ((x >> 5) != r.q) {
+        r.q += 1;
+        r.cur = r.nxt;
+        r.nxt = a.packed[r.q + 1];   // x < n_bytes, so q + 1 <= n_words: a padded word
+    }
+    const uint32_t b = (uint32_t)((r.cur >> (62 - 2 * (x & 31))) & 3ull);
     roll_base<W>(r.fw, r.rc, b, a.k);
 }
 
@@ -695,8 +705,13 @@ __global__ void __launch_bounds__(kLdsBlock) k_lds_persistent(CountArgs a, LdsAr
             if (st == 3) wait_done(l.done + 4 * r + 2, l.rank_nchunk[r], kLdsWait, a.status, ST_SPIN);
         }
         __syncthreads();
+        const uint64_t t0 = l.stage_clocks ? wall_clock64() : 0;
         run_stage<W>(a, l, s, st, r, local, wmax);
         signal_done(l.done + 4 * r + st);
+        if (l.stage_clocks && tid == 0) {
+            add_dev(&l.stage_clocks[st], wall_clock64() - t0);
+            add_dev(&l.stage_clocks[4 + st], 1ull);
+        }
         __syncthreads();
     }
     hist_end(a, s, wmax);
