@@ -12,8 +12,10 @@
 //
 // GPU design: the read stream is cut into tiles of kTile k-mer start
 // positions. A workgroup computes the m-mer ranks of its tile plus a halo of
-// w = k-m+1 positions, takes the sliding-window minimum over w by doubling
-// in LDS (log2 w steps), finds super-mer starts with wave ballots, and writes
+// w = k-m+1 positions (each thread rolls the canonical m-mer over a run of
+// positions), takes the minimum of every window of w ranks (each thread
+// covers a run of windows as suffix minimum + shared middle + prefix
+// minimum), finds super-mer starts with wave ballots, and writes
 // one descriptor per super-mer piece (super-mers are also cut at tile
 // boundaries; both pieces keep the same bin). Per-bin super-mer counts are
 // privatised in LDS. A scan and an LDS-privatised scatter then group the
@@ -27,20 +29,18 @@ constexpr uint32_t kBinBlock = 256;
 constexpr uint32_t kMaxW = 256;                 // w = k - m + 1 <= 256 for k <= 256
 constexpr uint32_t kRankLen = kTile + kMaxW;    // ranks for positions P0-1 .. P0+kTile-1+w-1
 constexpr uint32_t kWordsPerTile = kTile / 64;
-constexpr uint32_t kRankPerThread = (kRankLen + kBinBlock - 1) / kBinBlock;
 
-// Rank of the canonical m-mer starting at position j.
-__device__ __forceinline__ uint32_t mmer_rank(const uint64_t* __restrict__ P, int64_t j, uint32_t m, uint32_t order) {
-    uint64_t win = window32(P, j);
-    uint64_t fw = win >> (64 - 2 * m);
-    uint64_t rc = revcomp32(win) & ((1ull << (2 * m)) - 1ull);   // last m bases of the reversed window
+__device__ __forceinline__ uint32_t rank_of(uint64_t fw, uint64_t rc, uint32_t m, uint32_t order) {
     uint64_t c = fw < rc ? fw : rc;
     if (order == 0 && m >= 3) {
-        uint64_t head = c >> (2 * m - 6);   // first three bases
+        uint64_t head = c >> (2 * m - 6);
         if (head == 0 /* AAA */ || head == 4 /* ACA */) c += 1ull << (2 * m);
     }
     return (uint32_t)c;
 }
+
+constexpr uint32_t kRankPer = (kRankLen + kBinBlock - 1) / kBinBlock;     // ranks per thread
+constexpr uint32_t kMinPer = (kTile + 1 + kBinBlock - 1) / kBinBlock;      // minimizers per thread
 
 __global__ void __launch_bounds__(kBinBlock) k_bin_tiles(BinArgs a) {
     __shared__ uint32_t R[kRankLen];
@@ -63,33 +63,80 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_tiles(BinArgs a) {
     for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int64_t P0 = (int64_t)(tile * kTile);
         const uint32_t len = kTile + w;   // ranks R[i] for positions P0-1+i
-        // 1. ranks
-        for (uint32_t i = tid; i < len; i += kBinBlock) {
-            int64_t j = P0 - 1 + (int64_t)i;
-            R[i] = (j < (int64_t)n_pos) ? mmer_rank(a.packed, j, a.m, a.order) : 0xFFFFFFFFu;
+        // 1. ranks: every thread rolls the canonical m-mer over its own run of positions
+        {
+            const uint32_t i0 = tid * kRankPer;
+            const uint32_t i1 = i0 + kRankPer < len ? i0 + kRankPer : len;
+            const uint64_t mmask = (1ull << (2 * a.m)) - 1ull;
+            uint64_t fw = 0, rc = 0, cur = 0, nxt = 0;
+            int64_t q = 0;
+            for (uint32_t i = i0; i < i1; i++) {
+                const int64_t j = P0 - 1 + (int64_t)i;
+                if (j >= (int64_t)n_pos) {
+                    R[i] = 0xFFFFFFFFu;
+                    continue;
+                }
+                if (i == i0) {
+                    const uint64_t win = window32(a.packed, j);
+                    fw = win >> (64 - 2 * a.m);
+                    rc = revcomp32(win) & mmask;
+                    q = (j + a.m) >> 5;            // word of the next base to enter
+                    cur = a.packed[q];
+                    nxt = a.packed[q + 1];         // j < n_pos: q + 1 <= n_words + 1, a padded word
+                } else {
+                    const int64_t x = j + a.m - 1;  // the base that enters the m-mer
+                    if ((x >> 5) != q) {
+                        q += 1;
+                        cur = nxt;
+                        nxt = a.packed[q + 1];
+                    }
+                    const uint64_t b2 = (cur >> (62 - 2 * (x & 31))) & 3ull;
+                    fw = ((fw << 2) | b2) & mmask;
+                    rc = (rc >> 2) | ((3ull - b2) << (2 * a.m - 2));
+                }
+                R[i] = rank_of(fw, rc, a.m, a.order);
+            }
         }
         __syncthreads();
-        // 2. sliding minimum over w by doubling: after a step R[i] = min over [i, i+2s)
-        uint32_t span = 1;
-        while (2 * span <= w) {
-            uint32_t v[kRankPerThread];
+        // 2. minimizer of the k-mer at P0-1+i = min R[i .. i+w): each thread takes
+        //    a run of kMinPer positions; their windows share the middle part.
+        {
+            const uint32_t i0 = tid * kMinPer;
+            const uint32_t i1 = i0 + kMinPer < kTile + 1 ? i0 + kMinPer : kTile + 1;
+            if (i0 < i1) {
+                if (w <= 2 * kMinPer) {
+                    for (uint32_t i = i0; i < i1; i++) {
+                        uint32_t mn = 0xFFFFFFFFu;
+                        for (uint32_t t = 0; t < w; t++) mn = min(mn, R[i + t]);
+                        M[i] = mn;
+                    }
+                } else {
+                    // window [i, i+w) = [i, i1-1) + [i1-1, i0+w) + [i0+w, i+w)
+                    uint32_t mid = 0xFFFFFFFFu;
+                    for (uint32_t t = i1 - 1; t < i0 + w; t++) mid = min(mid, R[t]);
+                    uint32_t suf[kMinPer], pre[kMinPer];
+                    uint32_t run = 0xFFFFFFFFu;
 #pragma unroll
-            for (uint32_t e = 0; e < kRankPerThread; e++) {
-                uint32_t i = tid + e * kBinBlock;
-                v[e] = 0;
-                if (i + span < len) v[e] = min(R[i], R[i + span]);
-            }
-            __syncthreads();
+                    for (int e = kMinPer - 1; e >= 0; e--) {   // suffix minima of [i, i1-1)
+                        const uint32_t i = i0 + e;
+                        if (i + 1 < i1) run = min(run, R[i]);
+                        suf[e] = run;
+                    }
+                    run = 0xFFFFFFFFu;
 #pragma unroll
-            for (uint32_t e = 0; e < kRankPerThread; e++) {
-                uint32_t i = tid + e * kBinBlock;
-                if (i + span < len) R[i] = v[e];
+                    for (int e = 0; e < (int)kMinPer; e++) {   // prefix minima of [i0+w, i+w)
+                        pre[e] = run;
+                        const uint32_t t = i0 + w + e;
+                        if (i0 + e + 1 < i1) run = min(run, R[t]);
+                    }
+#pragma unroll
+                    for (int e = 0; e < (int)kMinPer; e++) {
+                        const uint32_t i = i0 + e;
+                        if (i < i1) M[i] = min(min(suf[e], mid), pre[e]);
+                    }
+                }
             }
-            __syncthreads();
-            span *= 2;
         }
-        // minimizer of the k-mer at P0-1+i covers ranks [i, i+w)
-        for (uint32_t i = tid; i <= kTile; i += kBinBlock) M[i] = min(R[i], R[i + w - span]);
         __syncthreads();
         // 3. super-mer starts and ends (ballot per 64 positions)
         for (uint32_t c = wave; c < kWordsPerTile; c += kBinBlock / 64) {

@@ -217,64 +217,66 @@ __device__ __forceinline__ Lds lds_carve(uint8_t* base) {
     return x;
 }
 
-// Descriptor chunk `chunk` of bin b: one descriptor per thread; exclusive
-// prefix of the k-mer counts in spre[0..kLdsBlock] (spre[kLdsBlock] = total),
-// first positions in sstart.
-__device__ __forceinline__ uint32_t load_chunk(const CountArgs& a, const LdsArgs& l, uint32_t b, uint32_t chunk,
-                                               int64_t* sstart, uint32_t* spre, uint32_t* wsum) {
+// Descriptor chunk `chunk` of bin b, one descriptor per thread, with every
+// super-mer cut into segments of at most L k-mers: sdesc[d] is descriptor d,
+// sgpre[d] the first segment of d (sgpre[kLdsBlock] = number of segments).
+__device__ __forceinline__ uint32_t load_chunk_seg(const CountArgs& a, const LdsArgs& l, uint32_t b, uint32_t chunk,
+                                                   uint32_t L, uint64_t* sdesc, uint32_t* sgpre, uint32_t* wsum) {
     const uint32_t tid = threadIdx.x;
     const uint64_t d_end = l.bin_off[b + 1];
     const uint64_t i = l.bin_off[b] + (uint64_t)chunk * kLdsBlock + tid;
-    uint32_t n = 0;
-    int64_t st = 0;
-    if (i < d_end) {
-        uint64_t d = a.desc[i];
-        st = (int64_t)(d >> 24);
-        n = (uint32_t)(d & 0xFFFFFFu);
-    }
+    const uint64_t d = i < d_end ? a.desc[i] : 0ull;
+    const uint32_t n = (uint32_t)(d & 0xFFFFFFu);
     uint32_t total;
-    uint32_t pre = block_excl_scan(n, wsum, total);
-    sstart[tid] = st;
-    spre[tid] = pre;
-    if (tid == 0) spre[kLdsBlock] = total;
+    const uint32_t pre = block_excl_scan((n + L - 1) / L, wsum, total);
+    sdesc[tid] = d;
+    sgpre[tid] = pre;
+    if (tid == 0) sgpre[kLdsBlock] = total;
     __syncthreads();
     return total;
 }
 
-// A rolling window over consecutive k-mers of a chunk: the forward and
-// reverse-complement keys are shifted by one base per k-mer (Sec. 2.3.2
-// splitter step) instead of being re-read from the packed reads.
+// A segment of consecutive k-mers of one super-mer, rolled one base at a time
+// (Sec. 2.3.2 splitter step): the first k-mer is read from the packed reads,
+// every following one shifts one base into the forward key and its
+// complement into the reverse-complement key. A segment adds at most 32 new
+// bases, all inside the two packed words read at its start, so rolling never
+// waits for memory.
+constexpr uint32_t kSegMax = 32;
+
 template <int W>
-struct Roller {
+struct Segment {
     uint64_t fw[W], rc[W];
-    int64_t p;        // position of the current k-mer
-    uint32_t next;    // chunk k-mer index at which the next super-mer starts
-    bool ok;          // the super-mer lies inside the reads
-    int64_t q;        // packed word holding the next base to shift in
-    uint64_t cur, nxt;   // packed words q and q+1 (nxt is fetched 32 bases before it is used)
+    int64_t p;         // position of the current k-mer
+    uint32_t len;      // k-mers in the segment
+    int64_t q;         // packed word holding the next base to shift in
+    uint64_t cur, nxt;
+    bool ok;
 };
 
 template <int W>
-__device__ __forceinline__ void roll_seek(const CountArgs& a, const int64_t* sstart, const uint32_t* spre, uint32_t idx,
-                                          Roller<W>& r) {
-    uint32_t lo = 0, hi = kLdsBlock;   // last descriptor whose prefix is <= idx
+__device__ __forceinline__ void seg_open(const CountArgs& a, const uint64_t* sdesc, const uint32_t* sgpre, uint32_t sg,
+                                         uint32_t L, Segment<W>& g) {
+    uint32_t lo = 0, hi = kLdsBlock;   // last descriptor whose first segment is <= sg
     while (hi - lo > 1) {
         uint32_t mid = (lo + hi) >> 1;
-        if (spre[mid] <= idx) lo = mid; else hi = mid;
+        if (sgpre[mid] <= sg) lo = mid; else hi = mid;
     }
-    uint32_t nxt = spre[lo + 1];
-    r.next = nxt;
-    r.p = sstart[lo] + (int64_t)(idx - spre[lo]);
-    const int64_t last = sstart[lo] + (int64_t)(nxt - spre[lo]) - 1;   // position of the super-mer's last k-mer
-    r.ok = sstart[lo] >= 0 && (uint64_t)last + a.k <= a.n_bytes;
-    if (!r.ok) {
+    const uint64_t d = sdesc[lo];
+    const int64_t start = (int64_t)(d >> 24);
+    const uint32_t n = (uint32_t)(d & 0xFFFFFFu);
+    const uint32_t off = (sg - sgpre[lo]) * L;
+    g.p = start + off;
+    g.len = n - off < L ? n - off : L;
+    g.ok = start >= 0 && (uint64_t)(g.p + g.len - 1) + a.k <= a.n_bytes;
+    if (!g.ok) {
         set_status(a.status, ST_SPIN);   // a corrupt descriptor must not read out of range
         return;
     }
-    extract_kmer<W>(a.packed, r.p, a.k, r.fw, r.rc);
-    r.q = (r.p + (int64_t)a.k) >> 5;   // next base: position p + k (< n_bytes + 1, so q + 1 is a padded word)
-    r.cur = a.packed[r.q];
-    r.nxt = a.packed[r.q + 1];
+    extract_kmer<W>(a.packed, g.p, a.k, g.fw, g.rc);
+    g.q = (g.p + (int64_t)a.k) >> 5;   // p + k <= n_bytes, so q + 1 is at most a padded word
+    g.cur = a.packed[g.q];
+    g.nxt = a.packed[g.q + 1];
 }
 
 // Shift in base b (code 0..3) at the end of the forward key and its
@@ -299,32 +301,17 @@ __device__ __forceinline__ void roll_base(uint64_t (&fw)[W], uint64_t (&rc)[W], 
     }
 }
 
-// Move the roller to chunk k-mer index idx, the index after the previous one.
+// Advance to the next k-mer of the segment.
 template <int W>
-__device__ __forceinline__ void roll_next(const CountArgs& a, const int64_t* sstart, const uint32_t* spre,
-                                          uint32_t idx, Roller<W>& r) {
-    if (idx >= r.next) {
-        roll_seek<W>(a, sstart, spre, idx, r);
-        return;
+__device__ __forceinline__ void seg_step(uint32_t k, Segment<W>& g) {
+    g.p += 1;
+    const int64_t x = g.p + (int64_t)k - 1;   // the base that enters the window
+    if ((x >> 5) != g.q) {
+        g.q += 1;
+        g.cur = g.nxt;
     }
-    r.p += 1;
-    if (!r.ok) return;
-    const int64_t x = r.p + (int64_t)a.k - 1;   // the base that enters the window
-    if ((x >> 5) != r.q) {
-        r.q += 1;
-        r.cur = r.nxt;
-        r.nxt = a.packed[r.q + 1];   // x < n_bytes, so q + 1 <= n_words: a padded word
-    }
-    const uint32_t b = (uint32_t)((r.cur >> (62 - 2 * (x & 31))) & 3ull);
-    roll_base<W>(r.fw, r.rc, b, a.k);
-}
-
-// Contiguous range of chunk k-mers handled by this thread.
-__device__ __forceinline__ void thread_range(uint32_t total, uint32_t& i0, uint32_t& i1) {
-    const uint32_t m = (total + kLdsBlock - 1) / kLdsBlock;
-    i0 = threadIdx.x * m;
-    i1 = i0 + m < total ? i0 + m : total;
-    if (i0 > total) i0 = total;
+    const uint32_t b = (uint32_t)((g.cur >> (62 - 2 * (x & 31))) & 3ull);
+    roll_base<W>(g.fw, g.rc, b, k);
 }
 
 // Exclusive prefix of cnt[0..n) into pre[0..n) by the whole block; returns the total.
@@ -344,29 +331,31 @@ __device__ __forceinline__ uint32_t block_scan_array(const uint32_t* cnt, uint32
     return total;
 }
 
-// Round size of the scatter stage: R keys per thread, staged in 96 KB of LDS at most.
+// Round size of the scatter stage: R keys per thread (one segment of at most
+// R k-mers), staged in 96 KB of LDS at most.
 template <int W>
 struct ScatterRound { static constexpr int R = W == 1 ? 8 : W == 2 ? 6 : W == 3 ? 4 : W == 4 ? 3 : W == 5 ? 2 : 1; };
 
-// LDS of the chunk stages: descriptor starts, prefixes and scan scratch.
+// LDS of the chunk stages: descriptors, segment prefixes and scan scratch.
 constexpr uint32_t kChunkHeader = 8 * kLdsBlock + 4 * (kLdsBlock + 4) + 4 * 32;
 
 struct ChunkLds {
-    int64_t* sstart;
-    uint32_t* spre;
+    uint64_t* sdesc;
+    uint32_t* sgpre;
     uint32_t* wsum;
     uint8_t* rest;
 };
 __device__ __forceinline__ ChunkLds chunk_lds(const Lds& s) {
     ChunkLds c;
-    c.sstart = (int64_t*)s.u;
-    c.spre = (uint32_t*)(s.u + 8 * kLdsBlock);
-    c.wsum = c.spre + kLdsBlock + 4;
+    c.sdesc = (uint64_t*)s.u;
+    c.sgpre = (uint32_t*)(s.u + 8 * kLdsBlock);
+    c.wsum = c.sgpre + kLdsBlock + 4;
     c.rest = (uint8_t*)(c.wsum + 32);
     return c;
 }
 
-// Stage A: keys of this slice per sub-table.
+// Stage A: keys of this slice per sub-table. One segment of up to 32 k-mers
+// per thread and round, so all lanes read their first k-mer together.
 template <int W>
 __device__ void stage_count(const CountArgs& a, const LdsArgs& l, const Lds& s, uint32_t r, uint32_t chunk) {
     const uint32_t tid = threadIdx.x;
@@ -375,19 +364,19 @@ __device__ void stage_count(const CountArgs& a, const LdsArgs& l, const Lds& s, 
     static_assert(kChunkHeader + 4 * kLdsMaxSub <= kLdsBytes - kLdsReserved, "count stage exceeds the LDS budget");
     uint32_t* hist = (uint32_t*)c.rest;
     for (uint32_t j = tid; j < P; j += kLdsBlock) hist[j] = 0;
-    const uint32_t total = load_chunk(a, l, b, chunk, c.sstart, c.spre, c.wsum);
-    uint32_t i0, i1;
-    thread_range(total, i0, i1);
-    Roller<W> ro;
-    for (uint32_t i = i0; i < i1; i++) {
-        if (i == i0) roll_seek<W>(a, c.sstart, c.spre, i, ro);
-        else roll_next<W>(a, c.sstart, c.spre, i, ro);
-        if (!ro.ok) continue;
-        uint64_t key[W];
-        canonical_of<W>(ro.fw, ro.rc, key);
-        const uint64_t h = key_hash<W>(key, a.seed);
-        if (V > 1 && slice_of(h, V) != v) continue;
-        atomicAdd(&hist[sub_of(h, P)], 1u);
+    const uint32_t S = load_chunk_seg(a, l, b, chunk, kSegMax, c.sdesc, c.sgpre, c.wsum);
+    for (uint32_t sg = tid; sg < S; sg += kLdsBlock) {
+        Segment<W> g;
+        seg_open<W>(a, c.sdesc, c.sgpre, sg, kSegMax, g);
+        if (!g.ok) continue;
+        for (uint32_t j = 0; j < g.len; j++) {
+            if (j) seg_step<W>(a.k, g);
+            uint64_t key[W];
+            canonical_of<W>(g.fw, g.rc, key);
+            const uint64_t h = key_hash<W>(key, a.seed);
+            if (V > 1 && slice_of(h, V) != v) continue;
+            atomicAdd(&hist[sub_of(h, P)], 1u);
+        }
     }
     __syncthreads();
     const uint64_t sb = l.rank_spbase[r];
@@ -430,9 +419,9 @@ __device__ void stage_scan(const CountArgs& a, const LdsArgs& l, const Lds& s, u
 }
 
 // Stage C: write the keys of this slice into their sub-table runs. Per round
-// every thread rolls R k-mers; the round's keys are grouped by sub-table in
-// LDS, one global reservation is made per sub-table, and each run is written
-// as consecutive words (coalesced stores).
+// every thread takes one segment of up to R k-mers (keys held in registers);
+// the round's keys are grouped by sub-table in LDS, one global reservation is
+// made per sub-table, and each run is written as consecutive words.
 template <int W>
 __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s, uint32_t r, uint32_t chunk) {
     constexpr int R = ScatterRound<W>::R;
@@ -448,28 +437,28 @@ __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s
     uint32_t* dst = lp + kLdsMaxSub;   // run start of this round, relative to the key slot
     uint64_t* buf = (uint64_t*)(dst + kLdsMaxSub);
     for (uint32_t j = tid; j < P; j += kLdsBlock) cnt[j] = 0;
-    const uint32_t total = load_chunk(a, l, b, chunk, c.sstart, c.spre, c.wsum);
-    uint32_t i0, i1;
-    thread_range(total, i0, i1);
-    const uint32_t m = (total + kLdsBlock - 1) / kLdsBlock;
-    const uint32_t rounds = (m + R - 1) / R;
-    Roller<W> ro;
+    const uint32_t S = load_chunk_seg(a, l, b, chunk, R, c.sdesc, c.sgpre, c.wsum);
+    const uint32_t rounds = (S + kLdsBlock - 1) / kLdsBlock;
     for (uint32_t round = 0; round < rounds; round++) {
         uint64_t key[R][W];
         uint32_t sp[R], rk[R];
 #pragma unroll
-        for (int e = 0; e < R; e++) {
-            sp[e] = kNone;
-            const uint32_t i = i0 + round * R + e;
-            if (i < i1) {
-                if (i == i0) roll_seek<W>(a, c.sstart, c.spre, i, ro);
-                else roll_next<W>(a, c.sstart, c.spre, i, ro);
-                if (ro.ok) {
-                    canonical_of<W>(ro.fw, ro.rc, key[e]);
-                    const uint64_t h = key_hash<W>(key[e], a.seed);
-                    if (V == 1 || slice_of(h, V) == v) {
-                        sp[e] = sub_of(h, P);
-                        rk[e] = atomicAdd(&cnt[sp[e]], 1u);
+        for (int e = 0; e < R; e++) sp[e] = kNone;
+        const uint32_t sg = round * kLdsBlock + tid;
+        if (sg < S) {
+            Segment<W> g;
+            seg_open<W>(a, c.sdesc, c.sgpre, sg, R, g);
+            if (g.ok) {
+#pragma unroll
+                for (int e = 0; e < R; e++) {
+                    if ((uint32_t)e < g.len) {
+                        if (e) seg_step<W>(a.k, g);
+                        canonical_of<W>(g.fw, g.rc, key[e]);
+                        const uint64_t h = key_hash<W>(key[e], a.seed);
+                        if (V == 1 || slice_of(h, V) == v) {
+                            sp[e] = sub_of(h, P);
+                            rk[e] = atomicAdd(&cnt[sp[e]], 1u);
+                        }
                     }
                 }
             }
@@ -480,8 +469,8 @@ __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s
         for (uint32_t j = tid; j < P; j += kLdsBlock) {
             const uint32_t n = cnt[j];
             if (n) {
-                const uint32_t g = add_dev(&l.sp_cur[sb + j], n);
-                dst[j] = (uint32_t)(ld_dev(&l.sp_off[sb + j]) + g);
+                const uint32_t gsub = add_dev(&l.sp_cur[sb + j], n);
+                dst[j] = (uint32_t)(ld_dev(&l.sp_off[sb + j]) + gsub);
                 cnt[j] = 0;
             }
         }
@@ -499,10 +488,10 @@ __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s
                 uint32_t mid = (lo + hi) >> 1;
                 if (lp[mid] <= i) lo = mid; else hi = mid;
             }
-            const uint64_t g = (uint64_t)dst[lo] + (i - lp[lo]);
-            if (g < l.slot_keys) {
+            const uint64_t gpos = (uint64_t)dst[lo] + (i - lp[lo]);
+            if (gpos < l.slot_keys) {
 #pragma unroll
-                for (int w = 0; w < W; w++) st_dev(&slot[g * W + w], buf[(uint64_t)i * W + w]);
+                for (int w = 0; w < W; w++) st_dev(&slot[gpos * W + w], buf[(uint64_t)i * W + w]);
             } else {
                 set_status(a.status, ST_POOL);
             }
