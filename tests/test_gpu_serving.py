@@ -1,0 +1,67 @@
+"""Serving loop: every job's result is the same alone and in the mix
+(tolerance 0: identical pairs and histograms), and matches the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_1607_06618_amd import gerbil as g
+from paper_1607_06618_amd import serve
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    g.load()
+
+
+def _requests(n_jobs, scale, arrivals):
+    reqs, data = [], []
+    for j in range(n_jobs):
+        w = synth.serving_job(j, scale=scale)
+        a, o = w.generate()
+        data.append((w, a, o))
+        reqs.append(serve.make_request(j, a, o, w.k, w.m, w.n_bins, w.threshold, arrival=float(arrivals[j])))
+    return reqs, data
+
+
+def test_alone_equals_mix_and_oracle():
+    n = 6
+    arrivals = synth.arrival_times(n) * 0.0   # all at once: maximal overlap
+    reqs, data = _requests(n, 0.02, arrivals)
+    alone = []
+    for r in reqs:
+        srv = serve.CountingServer(budget_bytes=64 << 30, max_inflight=1)
+        alone.extend(srv.serve([r], realtime=False))
+    srv = serve.CountingServer(budget_bytes=64 << 30, max_inflight=4)
+    mixed = srv.serve(reqs, realtime=False)
+    assert len(mixed) == n
+    ks = sorted({d[0].k for d in data})
+    assert len(ks) >= 2, "the mix should hold jobs of different k"
+    for a_res, m_res, (w, a, o) in zip(alone, mixed, data):
+        ka, ca = a_res.sorted()
+        km, cm = m_res.sorted()
+        assert np.array_equal(ka, km) and np.array_equal(ca, cm)
+        assert np.array_equal(a_res.hist, m_res.hist)
+        ref = oracle.count(a, o, w.k, threshold=w.threshold)
+        assert np.array_equal(ka, ref.keys) and np.array_equal(ca, ref.counts)
+        assert np.array_equal(a_res.hist, ref.folded_hist(1024))
+
+
+def test_admission_respects_the_budget_and_output_retry():
+    n = 4
+    reqs, data = _requests(n, 0.01, np.zeros(n))
+    # a budget below any single job still admits one job at a time (never zero)
+    srv = serve.CountingServer(budget_bytes=1, max_inflight=4)
+    res = srv.serve(reqs, realtime=False)
+    assert [r.job_id for r in res] == list(range(n))
+    stats = serve.summarize(res, srv.makespan)
+    assert stats["jobs"] == n and stats["p99_latency_s"] >= stats["p50_latency_s"] > 0
+    for r, (w, a, o) in zip(res, data):
+        ref = oracle.count(a, o, w.k, threshold=w.threshold)
+        k_, c_ = r.sorted()
+        assert np.array_equal(k_, ref.keys) and np.array_equal(c_, ref.counts)
