@@ -34,13 +34,21 @@ def parse_args(argv=None):
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="c2_k65")
     ap.add_argument("--scale", type=float, default=1.0, help="genome scale factor (1.0 = the named workload)")
-    ap.add_argument("--modes", default="batched,plain")
+    ap.add_argument("--modes", default="batched,plain,graph",
+                    help="batched: persistent counter; plain: one launch sequence per bin; "
+                         "graph: the batched path replayed from one HIP graph")
     ap.add_argument("--pool", type=int, default=0)
     ap.add_argument("--load", type=float, default=0.0)
     ap.add_argument("--table", default="lds", choices=["lds", "hbm"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tune", action="store_true", help="autotune the batched schedule before timing it")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes three times (calibrates HBM byte counters)")
     ap.add_argument("--stage-clocks", action="store_true", help="report busy time per LDS stage (batched)")
+    ap.add_argument("--serving", type=int, default=0, help="also serve this many jobs of the Poisson job stream")
+    ap.add_argument("--serving-scale", type=float, default=1.0, help="genome-size scale of the served jobs")
+    ap.add_argument("--serving-inflight", type=int, default=4)
     return ap.parse_args(argv)
 
 
@@ -71,6 +79,53 @@ class HipEvents:
         if rc != 0:
             raise RuntimeError(f"hipEventElapsedTime failed ({rc})")
         return float(ms.value)
+
+
+# Kernel sources whose change invalidates the measured HBM traffic of the counting kernel.
+TRAFFIC_SOURCES = ["paper_1607_06618_amd/csrc/lds.hip", "paper_1607_06618_amd/csrc/common.h",
+                   "paper_1607_06618_amd/csrc/internal.h", "paper_1607_06618_amd/csrc/table.h"]
+
+
+def sources_digest(paths) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in paths:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(rel.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed counter summary of `kernel` on
+    `workload`, or None if there is none or the kernel changed since."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for ln in f:
+            if ":" in ln and not ln.startswith("#"):
+                key, _, v = ln.partition(":")
+                vals[key.strip()] = v.strip()
+    if vals.get("source_sha256") != sources_digest(TRAFFIC_SOURCES):
+        return None
+    try:
+        return int(float(vals["traffic_bytes"]))
+    except (KeyError, ValueError):
+        return None
+
+
+def calibrate_copy(nbytes: int) -> int:
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.int64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "copy", "bytes_read": src.numel() * 8, "bytes_written": dst.numel() * 8,
+                      "launches": 3}), flush=True)
+    return 0
 
 
 def percentile(xs, q):
@@ -111,6 +166,9 @@ def main(argv=None):
               f"(the multi-GPU sharding is a design note only)", file=sys.stderr, flush=True)
         return 2
 
+    if args.calibrate_copy:
+        return calibrate_copy(args.calibrate_copy)
+
     import numpy as np
     import torch
 
@@ -139,50 +197,74 @@ def main(argv=None):
 
     evs = HipEvents()
     modes = [m.strip() for m in args.modes.split(",") if m.strip()]
+    if not any(m in ("batched", "plain") for m in modes):
+        modes.insert(0, "batched")   # the roofline needs an eager run with kernel events
     results = {}
     shared_out = {}
+    stream = torch.cuda.Stream(device=dev)   # default priority; graph capture needs a non-NULL stream
     for mode_name in modes:
-        mode = g.GERBIL_BATCHED if mode_name == "batched" else g.GERBIL_PLAIN
+        graph = mode_name == "graph"   # the batched path replayed from a HIP graph
+        mode = g.GERBIL_PLAIN if mode_name == "plain" else g.GERBIL_BATCHED
         ev = evs.pair()
         table = g.GERBIL_TABLE_LDS if args.table == "lds" else g.GERBIL_TABLE_HBM
         p = g.make_params(w.k, w.m, w.n_bins, w.threshold, mode=mode, pool=args.pool, load_factor=args.load, table=table,
                           bin_map_ptr=bin_map_d.data_ptr() if bin_map_d is not None else 0,
                           timing_events=ctypes.addressof(ev))
         clocks_d = None
-        if args.stage_clocks and mode == g.GERBIL_BATCHED:
+        if args.stage_clocks and mode == g.GERBIL_BATCHED and not graph:
             clocks_d = torch.zeros(8, dtype=torch.int64, device=dev)
             p.stage_clocks = clocks_d.data_ptr()
-        job = g.Job(ascii_d, offsets_d, int(offsets[-1]), p, hist_len=65536)
-        # first pass sizes the workspaces (synchronises); outputs are shared between schedules
-        job.encode()
-        job.bin()
-        st, rep = g.gerbil_result(job.enc, job.bins, None)
-        if "keys" in shared_out:
-            job.cap, job.keys_d, job.counts_d = shared_out["cap"], shared_out["keys"], shared_out["counts"]
-        job.prepare_count(n_valid=rep.n_valid)
-        shared_out.update(cap=job.cap, keys=job.keys_d, counts=job.counts_d)
-        for _ in range(args.warmup):
-            job.run()
-        res = job.result()
-        torch.cuda.synchronize()
-        step_ms = []
-        starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-        kev = [evs.pair() for _ in range(args.steps)]   # counting-kernel events, one pair per step
-        torch.cuda.synchronize()
-        wall0 = time.perf_counter()
-        starts[0].record()
-        for s in range(args.steps):
-            job.p.timing_events = ctypes.cast(kev[s], ctypes.c_void_p)
-            job.run()
-            starts[s + 1].record()
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - wall0
+        with torch.cuda.stream(stream):
+            job = g.Job(ascii_d, offsets_d, int(offsets[-1]), p, hist_len=65536, stream=stream)
+            # first pass sizes the workspaces (synchronises); outputs are shared between schedules
+            job.encode()
+            job.bin()
+            st, rep = g.gerbil_result(job.enc, job.bins, None, g._stream_handle(stream))
+            if "keys" in shared_out:
+                job.cap, job.keys_d, job.counts_d = shared_out["cap"], shared_out["keys"], shared_out["counts"]
+            tune = None
+            if args.tune and mode == g.GERBIL_BATCHED:
+                info = job.autotune()
+                tune = {"table": {g.GERBIL_TABLE_LDS: "lds", g.GERBIL_TABLE_HBM: "hbm"}[info.table],
+                        "load_factor": round(info.load_factor, 3), "pool": info.pool,
+                        "candidates": info.candidates, "cached": bool(info.cached),
+                        "best_count_ms": round(info.best_ms, 3)}
+                print(f"[bench] {mode_name} autotune: {tune}", file=sys.stderr, flush=True)
+            job.prepare_count(n_valid=rep.n_valid)
+            shared_out.update(cap=job.cap, keys=job.keys_d, counts=job.counts_d)
+            for _ in range(args.warmup):
+                job.run()
+            res = job.result()
+            if graph:
+                job.capture()
+                job.replay()
+                res = job.result()
+            torch.cuda.synchronize()
+            step_ms = []
+            starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+            kev = [evs.pair() for _ in range(args.steps)]   # counting-kernel events, one pair per step
+            torch.cuda.synchronize()
+            wall0 = time.perf_counter()
+            starts[0].record(stream)
+            for s in range(args.steps):
+                if graph:
+                    job.replay()
+                else:
+                    job.p.timing_events = ctypes.cast(kev[s], ctypes.c_void_p)
+                    job.run()
+                starts[s + 1].record(stream)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - wall0
+            res_t = job.result()
+            job.close()
         for s in range(args.steps):
             step_ms.append(starts[s].elapsed_time(starts[s + 1]))
-        kms_all = [evs.elapsed_ms(e) for e in kev]
-        kms = sum(kms_all) / len(kms_all)
-        res_t = job.result()
-        results[mode_name] = dict(job=job, res=res_t, wall=wall, step_ms=step_ms, kernel_ms=kms, ev=ev)
+        kms = None
+        if not graph:
+            kms_all = [evs.elapsed_ms(e) for e in kev]
+            kms = sum(kms_all) / len(kms_all)
+        results[mode_name] = dict(job=job, res=res_t, wall=wall, step_ms=step_ms, kernel_ms=kms, ev=ev, tune=tune,
+                                  table=job.p.table)
         if clocks_d is not None:
             c = clocks_d.cpu().numpy()
             runs = args.warmup + args.steps
@@ -192,11 +274,13 @@ def main(argv=None):
             print(f"[bench] {mode_name} stage busy ms (summed over workgroups, per step): "
                   f"{results[mode_name]['stage_ms']} items {results[mode_name]['stage_items']}",
                   file=sys.stderr, flush=True)
-        print(f"[bench] {mode_name}: {args.steps} steps in {wall:.3f} s, step p50 {percentile(step_ms, 50):.2f} ms, "
-              f"counting kernel {kms:.2f} ms", file=sys.stderr, flush=True)
+        kdesc = f", counting kernel {kms:.2f} ms" if kms is not None else ""
+        print(f"[bench] {mode_name}: {args.steps} steps in {wall:.3f} s, step p50 {percentile(step_ms, 50):.2f} ms"
+              f"{kdesc}", file=sys.stderr, flush=True)
 
-    head = "batched" if "batched" in results else modes[0]
+    head = "batched" if "batched" in results else [m for m in modes if m != "graph"][0]
     R = results[head]
+    head_table = "hbm" if R["table"] == g.GERBIL_TABLE_HBM else "lds"
     rep = R["res"].report
     n_valid = rep.n_valid
     value = n_valid * args.steps / R["wall"]
@@ -206,9 +290,9 @@ def main(argv=None):
     c = np.arange(hist.size, dtype=np.float64)
     checks = {"sum_c_h_equals_valid": bool(rep.max_count < hist.size - 1 and int((c * hist).sum()) == n_valid)}
     if len(results) > 1:
-        other = [m for m in results if m != head][0]
-        o = results[other]["res"]
-        checks["modes_agree"] = bool(o.report.n_out == rep.n_out and np.array_equal(o.hist, R["res"].hist))
+        checks["modes_agree"] = all(
+            bool(results[m]["res"].report.n_out == rep.n_out and np.array_equal(results[m]["res"].hist, R["res"].hist))
+            for m in results if m != head)
 
     # Algorithmic bytes of one counting launch: the super-mer bases read
     # (2 bits per base, n_kmers + k - 1 bases per super-mer), every distinct
@@ -220,9 +304,13 @@ def main(argv=None):
     alg_bytes = b_in + 2.0 * E * n_distinct + E * rep.n_out
     achieved = alg_bytes / (R["kernel_ms"] / 1000.0) / 1e9
     kname = {("batched", "lds"): "k_lds_persistent", ("plain", "lds"): "k_lds_stage",
-             ("batched", "hbm"): "k_count_persistent", ("plain", "hbm"): "k_count_bin+k_compact"}[(head, args.table)]
+             ("batched", "hbm"): "k_count_persistent", ("plain", "hbm"): "k_count_bin+k_compact"}[(head, head_table)]
+    traffic = None
+    default_schedule = not args.tune and args.load == 0.0 and args.pool == 0 and args.scale == 1.0
+    if default_schedule and "+" not in kname:
+        traffic = measured_traffic(kname, w.name)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kname,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
                 "kernel_ms": round(R["kernel_ms"], 3), "alg_bytes": int(alg_bytes),
                 "alg_bytes_per_window": round(alg_bytes / max(1, n_valid), 2)}
 
@@ -237,7 +325,7 @@ def main(argv=None):
         "config": {"workload": w.name, "description": w.note, "k": w.k, "m": w.m, "n_bins": w.n_bins,
                    "threshold": w.threshold, "reads": int(offsets.size - 1), "bytes": int(ascii_.size),
                    "valid_windows": int(n_valid), "super_mers": int(rep.n_superm), "distinct": n_distinct,
-                   "pairs_out": int(rep.n_out), "schedule": head, "table": args.table},
+                   "pairs_out": int(rep.n_out), "schedule": head, "table": head_table},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "p50_ms": percentile(R["step_ms"], 50), "p99_ms": percentile(R["step_ms"], 99),
@@ -246,14 +334,50 @@ def main(argv=None):
     for m, r in results.items():
         out[f"{m}_kmers_per_s"] = n_valid * args.steps / r["wall"]
         out[f"{m}_ms_per_step"] = 1000.0 * r["wall"] / args.steps
-        out[f"{m}_count_kernel_ms"] = r["kernel_ms"]
+        if r["kernel_ms"] is not None:
+            out[f"{m}_count_kernel_ms"] = r["kernel_ms"]
+        if r.get("tune"):
+            out[f"{m}_autotune"] = r["tune"]
         if "stage_ms" in r:
             out[f"{m}_stage_busy_ms"] = r["stage_ms"]
             out[f"{m}_stage_items"] = r["stage_items"]
     if "batched" in results and "plain" in results:
         out["batched_over_plain"] = results["plain"]["wall"] / results["batched"]["wall"]
+    if args.serving:
+        out["serving"] = run_serving(args)
     print(json.dumps(out), flush=True)
     return 0
+
+
+def run_serving(args):
+    """Poisson stream of independent jobs through the serving loop (arrival -> results on the host)."""
+    import concurrent.futures as cf
+
+    import synth
+    from paper_1607_06618_amd import serve
+
+    n = args.serving
+    arrivals = synth.arrival_times(n)
+
+    def make(j):
+        w = synth.serving_job(j, scale=args.serving_scale)
+        a, o = w.generate(threads=4)
+        return serve.make_request(j, a, o, w.k, w.m, w.n_bins, w.threshold, arrival=float(arrivals[j]))
+
+    t = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=4) as ex:
+        reqs = list(ex.map(make, range(n)))
+    gen_s = time.perf_counter() - t
+    import torch
+    free, total = torch.cuda.mem_get_info()
+    srv = serve.CountingServer(budget_bytes=int(free * 0.6), max_inflight=args.serving_inflight)
+    res = srv.serve(reqs, realtime=True)
+    stats = serve.summarize(res, srv.makespan)
+    stats.update({"offered_jobs_per_s": synth.SERVING_RATE, "scale": args.serving_scale,
+                  "inflight": args.serving_inflight, "generation_s": round(gen_s, 1),
+                  "k_mix": sorted({r.k for r in reqs})})
+    print(f"[bench] serving: {stats}", file=sys.stderr, flush=True)
+    return stats
 
 
 if __name__ == "__main__":

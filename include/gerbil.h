@@ -239,6 +239,101 @@ int32_t gerbil_histogram(const gerbil_counted* state, uint64_t* hist, uint32_t l
 int32_t gerbil_result(const gerbil_encoded* enc, const gerbil_bins* bins, const gerbil_counted* state,
                       gerbil_report* report, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Whole-path replay. The batched path (encode -> bin -> count -> histogram)
+ * is a fixed sequence of kernel launches with no host synchronisation, so
+ * for inputs of one shape it can be recorded once into a HIP graph and
+ * replayed with a single launch per batch (the paper's pipeline of
+ * Sec. 2.3 without per-step host work). Sizing needs the bin sizes, so
+ * gerbil_count_workspace must be called beforehand (an eager first run).
+ * ------------------------------------------------------------------------ */
+
+/* Buffers of one run of the whole path (all device pointers owned by the caller). */
+typedef struct {
+    const uint8_t* ascii;      /* device uint8 [n_bytes]                                   */
+    const uint64_t* offsets;   /* device uint64 [n_reads+1]                                */
+    uint64_t n_reads;
+    uint64_t n_bytes;
+    void* ws_encode;           /* gerbil_encode_workspace() bytes                          */
+    uint64_t ws_encode_bytes;
+    void* ws_bin;              /* gerbil_bin_workspace() bytes                             */
+    uint64_t ws_bin_bytes;
+    void* ws_count;            /* gerbil_count_workspace() bytes                           */
+    uint64_t ws_count_bytes;
+    uint64_t* keys;            /* device uint64 [cap * W]                                  */
+    uint32_t* counts;          /* device uint32 [cap]                                      */
+    uint64_t cap;
+    uint64_t* hist;            /* device uint64 [hist_len]                                 */
+    uint32_t hist_len;
+    uint32_t reserved;
+} gerbil_pipeline;
+
+typedef struct gerbil_graph gerbil_graph;
+
+/* Record encode -> bin -> count -> histogram of `pl` into a graph (stream
+ * capture on `stream`, which must not be the NULL stream; nothing runs
+ * during the capture). p->mode must be GERBIL_BATCHED (GERBIL_EUNSUPPORTED
+ * otherwise); p->timing_events is ignored. enc, bins and state are filled as
+ * by the individual calls and describe the results of every replay. The
+ * graph holds kernel nodes only (no memset or copy nodes); any other node
+ * makes the call fail with GERBIL_EUNSUPPORTED. On success *out owns a host
+ * object released by gerbil_graph_destroy; the buffers of `pl` must outlive it. */
+int32_t gerbil_graph_capture(const gerbil_pipeline* pl, const gerbil_params* p, gerbil_encoded* enc,
+                             gerbil_bins* bins, gerbil_counted* state, hipStream_t stream, gerbil_graph** out);
+
+/* Enqueue one replay on `stream`. Results and status are read with
+ * gerbil_result as after the individual calls. Replays on one graph must not
+ * overlap (they share the workspaces). */
+int32_t gerbil_graph_launch(const gerbil_graph* g, hipStream_t stream);
+
+/* Number of nodes, and of kernel nodes, in the recorded graph. */
+int32_t gerbil_graph_info(const gerbil_graph* g, uint32_t* n_nodes, uint32_t* n_kernel_nodes);
+
+/* Release the graph (NULL is ignored). The caller ensures no replay is still running. */
+int32_t gerbil_graph_destroy(gerbil_graph* g);
+
+/* ------------------------------------------------------------------------
+ * Autotuner. The paper chooses thread counts at run time and re-estimates
+ * table sizes from the data (Sec. 2.3; Sec. 3.4.2); here the schedule's
+ * free parameters are chosen by timing them on the caller's bins.
+ * ------------------------------------------------------------------------ */
+
+/* What gerbil_autotune chose. */
+typedef struct {
+    uint32_t table;          /* GERBIL_TABLE_LDS or GERBIL_TABLE_HBM                     */
+    float load_factor;       /* chosen gerbil_params.load_factor                         */
+    uint32_t pool;           /* chosen gerbil_params.pool (0 in PLAIN mode)              */
+    uint32_t candidates;     /* candidates timed (0 when the choice came from the cache) */
+    uint32_t cached;         /* 1 if the choice came from the cache                      */
+    float best_ms;           /* time of one gerbil_count with the choice                 */
+} gerbil_tune_result;
+
+/* Workspace bytes that fit every candidate of gerbil_autotune for these
+ * bins (the largest gerbil_count_workspace over them). SYNCHRONISES `stream`. */
+int32_t gerbil_autotune_workspace(const gerbil_bins* bins, const gerbil_params* p, uint64_t* bytes,
+                                  hipStream_t stream);
+
+/* Time gerbil_count on `bins` for each candidate of the grid (LDS tables:
+ * load_factor 0.6/0.7/0.8/0.9 x pool 4/8/16; HBM tables: load_factor 0.4/0.6
+ * x pool 8/32; p->table = LDS or HBM restricts the grid to that placement;
+ * PLAIN mode has no pool) and write into *best a copy of *p with table,
+ * load_factor and pool of the fastest candidate that finished without a
+ * capacity error. Candidates whose workspace exceeds ws_bytes are skipped.
+ * keys/counts/cap serve as the output of the trial runs (their contents are
+ * overwritten). The choice is cached per (device, ceil(k/32), m, n_bins,
+ * mode, p->table, and the total, largest and median bin size in quarter
+ * octaves); a later call with the same profile returns the cached choice
+ * without running anything (info->cached = 1). SYNCHRONISES `stream`.
+ * Errors: GERBIL_EINVAL (bad arguments, or no candidate fits ws_bytes),
+ * GERBIL_ECAPACITY (cap too small, or every candidate ran out of a
+ * capacity), GERBIL_EDEVICE. */
+int32_t gerbil_autotune(const gerbil_bins* bins, const gerbil_params* p, void* ws, uint64_t ws_bytes,
+                        uint64_t* keys, uint32_t* counts, uint64_t cap, gerbil_params* best,
+                        gerbil_tune_result* info, hipStream_t stream);
+
+/* Forget every cached autotuner choice. */
+int32_t gerbil_autotune_reset(void);
+
 #ifdef __cplusplus
 }
 #endif

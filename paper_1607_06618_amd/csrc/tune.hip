@@ -1,0 +1,195 @@
+// Autotuner of the counting schedule: times gerbil_count over a small grid
+// of table placements, fill levels and pool sizes on the caller's bins and
+// keeps the fastest choice that completes without a capacity error. Choices
+// are cached per (device, key width, m, bins, schedule, bin-size profile),
+// so later runs of the same shape skip the timing. The paper picks thread
+// counts at run time and re-estimates table sizes per file (Sec. 2.3,
+// Sec. 3.4.2); here the device-side analogs are tuned by measurement.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "gerbil.h"
+#include "common.h"
+
+namespace {
+
+struct Candidate {
+    uint32_t table;
+    float load;
+    uint32_t pool;
+};
+
+using Key = std::tuple<int, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, int, int, int>;
+
+std::mutex g_mu;
+std::map<Key, gerbil_tune_result> g_cache;
+
+int quarter_octave(uint64_t x) { return x ? (int)floor(4.0 * log2((double)x)) : -1; }
+
+std::vector<Candidate> candidates(const gerbil_params* p) {
+    std::vector<Candidate> c;
+    const bool batched = p->mode == GERBIL_BATCHED;
+    if (p->table != GERBIL_TABLE_HBM) {
+        const float fills[] = {0.6f, 0.7f, 0.8f, 0.9f};
+        const uint32_t pools[] = {4, 8, 16};
+        for (float f : fills) {
+            if (batched)
+                for (uint32_t q : pools) c.push_back({GERBIL_TABLE_LDS, f, q});
+            else
+                c.push_back({GERBIL_TABLE_LDS, f, 0});
+        }
+    }
+    if (p->table != GERBIL_TABLE_LDS) {
+        const float loads[] = {0.4f, 0.6f};
+        const uint32_t pools[] = {8, 32};
+        for (float f : loads) {
+            if (batched)
+                for (uint32_t q : pools) c.push_back({GERBIL_TABLE_HBM, f, q});
+            else
+                c.push_back({GERBIL_TABLE_HBM, f, 0});
+        }
+    }
+    return c;
+}
+
+gerbil_params apply(const gerbil_params* p, const Candidate& c) {
+    gerbil_params q = *p;
+    q.table = c.table;
+    q.load_factor = c.load;
+    q.pool = c.pool;
+    q.timing_events = nullptr;
+    q.stage_clocks = nullptr;
+    return q;
+}
+
+int32_t profile_key(const gerbil_bins* bins, const gerbil_params* p, hipStream_t stream, Key* key) {
+    std::vector<uint64_t> km(bins->n_bins);
+    if (hipMemcpyAsync(km.data(), bins->bin_kmers, 8 * (size_t)bins->n_bins, hipMemcpyDeviceToHost, stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+        return GERBIL_EDEVICE;
+    uint64_t total = 0;
+    for (uint64_t v : km) total += v;
+    std::sort(km.begin(), km.end());
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return GERBIL_EDEVICE;
+    *key = Key(dev, (p->k + 31) / 32, p->m, p->n_bins, p->mode, p->table, quarter_octave(total),
+               quarter_octave(km.back()), quarter_octave(km[km.size() / 2]));
+    return GERBIL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t gerbil_autotune_workspace(const gerbil_bins* bins, const gerbil_params* p, uint64_t* bytes,
+                                  hipStream_t stream) {
+    if (!bins || !p || !bytes) return GERBIL_EINVAL;
+    uint64_t mx = 0;
+    for (const Candidate& c : candidates(p)) {
+        gerbil_params q = apply(p, c);
+        uint64_t b = 0;
+        const int32_t st = gerbil_count_workspace(bins, &q, &b, stream);
+        if (st != GERBIL_OK) return st;
+        mx = std::max(mx, b);
+    }
+    *bytes = mx;
+    return GERBIL_OK;
+}
+
+int32_t gerbil_autotune(const gerbil_bins* bins, const gerbil_params* p, void* ws, uint64_t ws_bytes,
+                        uint64_t* keys, uint32_t* counts, uint64_t cap, gerbil_params* best,
+                        gerbil_tune_result* info, hipStream_t stream) {
+    if (!bins || !p || !ws || !best || (cap && (!keys || !counts))) return GERBIL_EINVAL;
+    uint64_t b0 = 0;
+    const int32_t st0 = gerbil_count_workspace(bins, p, &b0, stream);   // checks p against the bins
+    if (st0 != GERBIL_OK) return st0;
+    Key key;
+    int32_t st = profile_key(bins, p, stream, &key);
+    if (st != GERBIL_OK) return st;
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        auto it = g_cache.find(key);
+        if (it != g_cache.end()) {
+            *best = apply(p, Candidate{it->second.table, it->second.load_factor, it->second.pool});
+            best->timing_events = p->timing_events;
+            best->stage_clocks = p->stage_clocks;
+            if (info) {
+                *info = it->second;
+                info->cached = 1;
+            }
+            return GERBIL_OK;
+        }
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return GERBIL_EDEVICE;
+    }
+    gerbil_tune_result res;
+    memset(&res, 0, sizeof(res));
+    res.best_ms = INFINITY;
+    bool out_cap = false;
+    for (const Candidate& c : candidates(p)) {
+        gerbil_params q = apply(p, c);
+        uint64_t need = 0;
+        if (gerbil_count_workspace(bins, &q, &need, stream) != GERBIL_OK || need > ws_bytes) continue;
+        gerbil_counted state;
+        gerbil_report rep;
+        float ms_min = INFINITY;
+        bool ok = true;
+        for (int rep_i = 0; rep_i < 3 && ok; rep_i++) {   // the first run is a warm-up
+            if (hipEventRecord(e0, stream) != hipSuccess) { st = GERBIL_EDEVICE; break; }
+            st = gerbil_count(bins, &q, ws, need, keys, counts, cap, &state, stream);
+            if (st != GERBIL_OK) break;
+            if (hipEventRecord(e1, stream) != hipSuccess) { st = GERBIL_EDEVICE; break; }
+            const int32_t rs = gerbil_result(nullptr, nullptr, &state, &rep, stream);
+            if (rs == GERBIL_EDEVICE) { st = rs; break; }
+            if (rs != GERBIL_OK) {
+                if (rep.status & ST_OUT_CAP) out_cap = true;   // output capacity: not a property of the candidate
+                ok = false;
+                break;
+            }
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { st = GERBIL_EDEVICE; break; }
+            if (rep_i > 0) ms_min = std::min(ms_min, ms);
+        }
+        if (st == GERBIL_EDEVICE) break;
+        st = GERBIL_OK;
+        res.candidates++;
+        if (ok && ms_min < res.best_ms) {
+            res.best_ms = ms_min;
+            res.table = c.table;
+            res.load_factor = c.load;
+            res.pool = c.pool;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != GERBIL_OK) return st;
+    if (out_cap) return GERBIL_ECAPACITY;
+    if (!(res.best_ms < INFINITY)) return res.candidates ? GERBIL_ECAPACITY : GERBIL_EINVAL;
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        g_cache[key] = res;
+    }
+    *best = apply(p, Candidate{res.table, res.load_factor, res.pool});
+    best->timing_events = p->timing_events;
+    best->stage_clocks = p->stage_clocks;
+    if (info) *info = res;
+    return GERBIL_OK;
+}
+
+int32_t gerbil_autotune_reset(void) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_cache.clear();
+    return GERBIL_OK;
+}
+
+}  // extern "C"

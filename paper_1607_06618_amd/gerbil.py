@@ -73,6 +73,18 @@ class gerbil_report(ctypes.Structure):
                 ("status", u32), ("reserved", u32)]
 
 
+class gerbil_pipeline(ctypes.Structure):
+    _fields_ = [("ascii", vp), ("offsets", vp), ("n_reads", u64), ("n_bytes", u64), ("ws_encode", vp),
+                ("ws_encode_bytes", u64), ("ws_bin", vp), ("ws_bin_bytes", u64), ("ws_count", vp),
+                ("ws_count_bytes", u64), ("keys", vp), ("counts", vp), ("cap", u64), ("hist", vp),
+                ("hist_len", u32), ("reserved", u32)]
+
+
+class gerbil_tune_result(ctypes.Structure):
+    _fields_ = [("table", u32), ("load_factor", f32), ("pool", u32), ("candidates", u32), ("cached", u32),
+                ("best_ms", f32)]
+
+
 class GerbilError(RuntimeError):
     def __init__(self, fn: str, status: int, report: Optional[gerbil_report] = None):
         self.status = status
@@ -109,8 +121,19 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gerbil_count.argtypes = [P(gerbil_bins), P(gerbil_params), vp, u64, vp, vp, u64, P(gerbil_counted), vp]
     lib.gerbil_histogram.argtypes = [P(gerbil_counted), vp, u32, vp]
     lib.gerbil_result.argtypes = [P(gerbil_encoded), P(gerbil_bins), P(gerbil_counted), P(gerbil_report), vp]
+    lib.gerbil_graph_capture.argtypes = [P(gerbil_pipeline), P(gerbil_params), P(gerbil_encoded), P(gerbil_bins),
+                                         P(gerbil_counted), vp, P(vp)]
+    lib.gerbil_graph_launch.argtypes = [vp, vp]
+    lib.gerbil_graph_info.argtypes = [vp, P(u32), P(u32)]
+    lib.gerbil_graph_destroy.argtypes = [vp]
+    lib.gerbil_autotune_workspace.argtypes = [P(gerbil_bins), P(gerbil_params), P(u64), vp]
+    lib.gerbil_autotune.argtypes = [P(gerbil_bins), P(gerbil_params), vp, u64, vp, vp, u64, P(gerbil_params),
+                                    P(gerbil_tune_result), vp]
+    lib.gerbil_autotune_reset.argtypes = []
     for name in ("gerbil_encode_workspace", "gerbil_encode", "gerbil_bin_workspace", "gerbil_bin",
-                 "gerbil_count_workspace", "gerbil_count", "gerbil_histogram", "gerbil_result"):
+                 "gerbil_count_workspace", "gerbil_count", "gerbil_histogram", "gerbil_result",
+                 "gerbil_graph_capture", "gerbil_graph_launch", "gerbil_graph_info", "gerbil_graph_destroy",
+                 "gerbil_autotune_workspace", "gerbil_autotune", "gerbil_autotune_reset"):
         getattr(lib, name).restype = ctypes.c_int32
     _lib = lib
     return lib
@@ -181,6 +204,51 @@ def gerbil_result(enc: Optional[gerbil_encoded], bins: Optional[gerbil_bins], st
                               ctypes.byref(bins) if bins is not None else None,
                               ctypes.byref(state) if state is not None else None, ctypes.byref(rep), stream)
     return st, rep
+
+
+def gerbil_graph_capture(pl: gerbil_pipeline, p: gerbil_params, enc: gerbil_encoded, bins: gerbil_bins,
+                         state: gerbil_counted, stream: int):
+    """Returns (status, graph handle or None)."""
+    h = vp(0)
+    st = load().gerbil_graph_capture(ctypes.byref(pl), ctypes.byref(p), ctypes.byref(enc), ctypes.byref(bins),
+                                     ctypes.byref(state), stream, ctypes.byref(h))
+    return st, (h.value if st == GERBIL_OK else None)
+
+
+def gerbil_graph_launch(graph: int, stream: int) -> int:
+    return load().gerbil_graph_launch(graph, stream)
+
+
+def gerbil_graph_info(graph: int):
+    n, nk = u32(0), u32(0)
+    st = load().gerbil_graph_info(graph, ctypes.byref(n), ctypes.byref(nk))
+    return st, n.value, nk.value
+
+
+def gerbil_graph_destroy(graph: Optional[int]) -> int:
+    return load().gerbil_graph_destroy(graph)
+
+
+def gerbil_autotune_workspace(bins: gerbil_bins, p: gerbil_params, stream: int = 0) -> int:
+    out = u64(0)
+    st = load().gerbil_autotune_workspace(ctypes.byref(bins), ctypes.byref(p), ctypes.byref(out), stream)
+    if st:
+        raise GerbilError("gerbil_autotune_workspace", st)
+    return out.value
+
+
+def gerbil_autotune(bins: gerbil_bins, p: gerbil_params, ws_ptr: int, ws_bytes: int, keys_ptr: int,
+                    counts_ptr: int, cap: int, stream: int = 0):
+    """Returns (status, best params, tune result)."""
+    best = gerbil_params()
+    info = gerbil_tune_result()
+    st = load().gerbil_autotune(ctypes.byref(bins), ctypes.byref(p), ws_ptr, ws_bytes, keys_ptr, counts_ptr, cap,
+                                ctypes.byref(best), ctypes.byref(info), stream)
+    return st, best, info
+
+
+def gerbil_autotune_reset() -> int:
+    return load().gerbil_autotune_reset()
 
 
 def check(fn: str, status: int):
@@ -257,6 +325,7 @@ class Job:
         self.keys_d = None
         self.counts_d = None
         self.hist_d = torch.zeros(hist_len, dtype=torch.int64, device=dev)
+        self.graph = None
 
     def encode(self):
         s = _stream_handle(self.stream)
@@ -300,6 +369,52 @@ class Job:
         if self.ws_count is None or self.keys_d is None:
             self.prepare_count()
         self.count()
+
+    def autotune(self) -> gerbil_tune_result:
+        """Choose table placement, fill and pool by timing them on this job's bins
+        (after encode and bin); the job then counts with the choice."""
+        torch = self.torch
+        s = _stream_handle(self.stream)
+        need = gerbil_autotune_workspace(self.bins, self.p, s)
+        if self.ws_count is None or self.ws_count.numel() < need:
+            self.ws_count = torch.empty(need, dtype=torch.uint8, device=self.ascii_d.device)
+        self.prepare_count()
+        st, best, info = gerbil_autotune(self.bins, self.p, self.ws_count.data_ptr(), self.ws_count.numel(),
+                                         self.keys_d.data_ptr(), self.counts_d.data_ptr(), self.cap, s)
+        check("gerbil_autotune", st)
+        self.p = best
+        return info
+
+    def pipeline(self) -> gerbil_pipeline:
+        """Buffers of the whole path (sizes must have been taken by a first run)."""
+        if self.ws_bin is None or self.ws_count is None or self.keys_d is None:
+            raise RuntimeError("run the job once before capturing it: the count workspace is sized from the bins")
+        return gerbil_pipeline(ascii=self.ascii_d.data_ptr(), offsets=self.offsets_d.data_ptr(),
+                               n_reads=self.n_reads, n_bytes=self.n_bytes, ws_encode=self.ws_enc.data_ptr(),
+                               ws_encode_bytes=self.ws_enc.numel(), ws_bin=self.ws_bin.data_ptr(),
+                               ws_bin_bytes=self.ws_bin.numel(), ws_count=self.ws_count.data_ptr(),
+                               ws_count_bytes=self.ws_count.numel(), keys=self.keys_d.data_ptr(),
+                               counts=self.counts_d.data_ptr(), cap=self.cap, hist=self.hist_d.data_ptr(),
+                               hist_len=self.hist_len)
+
+    def capture(self):
+        """Record encode -> bin -> count -> histogram into a HIP graph (batched mode, non-default stream)."""
+        if self.graph is not None:
+            gerbil_graph_destroy(self.graph)
+            self.graph = None
+        self._pl = self.pipeline()
+        st, h = gerbil_graph_capture(self._pl, self.p, self.enc, self.bins, self.state, _stream_handle(self.stream))
+        check("gerbil_graph_capture", st)
+        self.graph = h
+        return h
+
+    def replay(self):
+        check("gerbil_graph_launch", gerbil_graph_launch(self.graph, _stream_handle(self.stream)))
+
+    def close(self):
+        if self.graph is not None:
+            gerbil_graph_destroy(self.graph)
+            self.graph = None
 
     def result(self, raise_on_error: bool = True) -> CountResult:
         st, rep = gerbil_result(self.enc, self.bins, self.state, _stream_handle(self.stream))

@@ -72,6 +72,7 @@ def test_struct_layout_matches_header(tmp_path):
     structs = {
         "gerbil_params": g.gerbil_params, "gerbil_encoded": g.gerbil_encoded, "gerbil_bins": g.gerbil_bins,
         "gerbil_counted": g.gerbil_counted, "gerbil_report": g.gerbil_report,
+        "gerbil_pipeline": g.gerbil_pipeline, "gerbil_tune_result": g.gerbil_tune_result,
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gerbil.h"', "int main(void) {"]
     for sname, cls in structs.items():
@@ -90,3 +91,27 @@ def test_struct_layout_matches_header(tmp_path):
         assert int(got[sname]) == ctypes.sizeof(cls), sname
         for fname, _ in cls._fields_:
             assert int(got[f"{sname}.{fname}"]) == getattr(cls, fname).offset, (sname, fname)
+
+
+def test_graph_capture_validation():
+    """Argument errors of the graph entry points come back before any device call."""
+    pl = g.gerbil_pipeline()
+    plain = g.make_params(32, 7, 64, 2, mode=g.GERBIL_PLAIN)
+    batched = g.make_params(32, 7, 64, 2, mode=g.GERBIL_BATCHED)
+    enc, bins, state = g.gerbil_encoded(), g.gerbil_bins(), g.gerbil_counted()
+    # the NULL stream cannot be recorded
+    st, h = g.gerbil_graph_capture(pl, batched, enc, bins, state, 0)
+    assert st == g.GERBIL_EINVAL and h is None
+    # only the batched path is free of host synchronisation
+    st, h = g.gerbil_graph_capture(pl, plain, enc, bins, state, 1)
+    assert st == g.GERBIL_EUNSUPPORTED and h is None
+    assert g.gerbil_graph_launch(None, 1) == g.GERBIL_EINVAL
+    assert g.gerbil_graph_info(None)[0] == g.GERBIL_EINVAL
+    assert g.gerbil_graph_destroy(None) == g.GERBIL_OK
+
+
+def test_autotune_validation():
+    p = g.make_params(32, 7, 64, 2, mode=g.GERBIL_BATCHED)
+    st, _, _ = g.gerbil_autotune(g.gerbil_bins(), p, 0, 0, 0, 0, 0, 1)
+    assert st == g.GERBIL_EINVAL
+    assert g.gerbil_autotune_reset() == g.GERBIL_OK
