@@ -74,7 +74,7 @@ uint64_t enc_layout(uint64_t n_bytes, void* ws, EncLayout* L) {
     l.valid = c.take<uint64_t>(n_mask + 1);
     l.read_start = c.take<uint64_t>(n_mask + 1);
     l.kmer_ok = c.take<uint64_t>(n_mask + 1);
-    l.scalars = c.take<uint64_t>(4);
+    l.scalars = c.take<uint64_t>(4);   // [0] n_superm [1] list slots handed out
     if (L) *L = l;
     return c.used;
 }
@@ -102,14 +102,14 @@ struct BinLayout {
 uint64_t bin_layout(uint64_t cap, uint32_t n_bins, void* ws, BinLayout* L) {
     Carve c(ws);
     BinLayout l;
-    l.list_desc = c.take<uint64_t>(cap);
-    l.list_bin = c.take<uint32_t>(cap);
+    l.list_desc = c.take<uint64_t>(cap + kListSlack);
+    l.list_bin = c.take<uint32_t>(cap + kListSlack);
     l.desc = c.take<uint64_t>(cap);
     l.bin_count = c.take<uint32_t>(n_bins);
     l.bin_fill = c.take<uint32_t>(n_bins);
     l.bin_off = c.take<uint64_t>(n_bins + 1);
     l.bin_kmers = c.take<uint64_t>(n_bins);
-    l.scalars = c.take<uint64_t>(4);
+    l.scalars = c.take<uint64_t>(4);   // [0] n_superm [1] list slots handed out
     if (L) *L = l;
     return c.used;
 }
@@ -504,8 +504,10 @@ int32_t gerbil_bin(const gerbil_encoded* enc, const gerbil_params* p, void* ws, 
     a.order = p->order;
     a.bin_map = p->bin_map;
     a.cap = cap;
+    a.list_cap = cap + kListSlack;
     a.list_desc = L.list_desc;
     a.list_bin = L.list_bin;
+    a.list_used = L.scalars + 1;
     a.n_superm = L.scalars;
     a.bin_count = L.bin_count;
     a.bin_fill = L.bin_fill;
@@ -517,6 +519,7 @@ int32_t gerbil_bin(const gerbil_encoded* enc, const gerbil_params* p, void* ws, 
     if (e == hipSuccess) e = launch_fill_u32(L.bin_count, p->n_bins, 0, stream);
     uint64_t n_tiles = (enc->n_bytes + kTile - 1) / kTile;
     uint64_t g = std::min<uint64_t>(std::max<uint64_t>(n_tiles, 1), (uint64_t)device_cus() * 8);
+    if (g > kMaxTileGrid) g = kMaxTileGrid;   // bounds the list's slack (one partial chunk per workgroup)
     if (e == hipSuccess) e = launch_bin(a, (uint32_t)g, stream);
     return hip_status(e);
 }

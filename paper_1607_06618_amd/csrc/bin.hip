@@ -41,14 +41,48 @@ __device__ __forceinline__ uint32_t rank_of(uint64_t fw, uint64_t rc, uint32_t m
 
 constexpr uint32_t kRankPer = (kRankLen + kBinBlock - 1) / kBinBlock;     // ranks per thread
 constexpr uint32_t kMinPer = (kTile + 1 + kBinBlock - 1) / kBinBlock;      // minimizers per thread
+// The bases a thread's ranks need (kRankPer m-mers, m <= 15) start at most 31
+// bases into a packed word, so they lie in that word and the next.
+static_assert(31 + kRankPer - 1 + 15 <= 64, "a rank run must fit in two packed words");
+static_assert(kWordsPerTile <= kBinBlock, "one bitmap word per thread");
+
+// Global data one tile needs, loaded one tile ahead into registers.
+struct TileFetch {
+    uint64_t w0, w1;   // the two packed words of this thread's rank run
+    uint64_t ok;       // threads < kWordsPerTile: one word of the valid-window bitmap
+};
+
+__device__ __forceinline__ TileFetch tile_fetch(const BinArgs& a, uint64_t tile, uint64_t n_tiles, uint64_t n_mask) {
+    TileFetch f{0ull, 0ull, 0ull};
+    if (tile >= n_tiles) return f;
+    const int64_t P0 = (int64_t)(tile * kTile);
+    const int64_t j0 = P0 - 1 + (int64_t)(threadIdx.x * kRankPer);
+    if (j0 < (int64_t)a.n_bytes) {   // j0 >= -1: word -1 is the zero pad; q + 1 <= n_words
+        const int64_t q = j0 >> 5;
+        f.w0 = a.packed[q];
+        f.w1 = a.packed[q + 1];
+    }
+    if (threadIdx.x < kWordsPerTile) {
+        const uint64_t qq = (uint64_t)(P0 >> 6) + threadIdx.x;
+        f.ok = qq < n_mask ? a.kmer_ok[qq] : 0ull;
+    }
+    return f;
+}
+
+// Base at offset o (0..63) of the 64-base pair (w0, w1).
+__device__ __forceinline__ uint64_t pair_base(uint64_t w0, uint64_t w1, uint32_t o) {
+    const uint64_t w = o < 32 ? w0 : w1;
+    return (w >> (62 - 2 * (o & 31))) & 3ull;
+}
 
 __global__ void __launch_bounds__(kBinBlock) k_bin_tiles(BinArgs a) {
     __shared__ uint32_t R[kRankLen];
     __shared__ uint32_t M[kTile + 1];
     __shared__ uint64_t brk[kWordsPerTile];
     __shared__ uint64_t stw[kWordsPerTile];
+    __shared__ uint64_t okS[kWordsPerTile];
     __shared__ uint32_t wpre[kWordsPerTile + 1];
-    __shared__ uint64_t tile_base;
+    __shared__ uint64_t tile_base, tile_split, tile_base2;
     extern __shared__ uint32_t bin_cnt[];   // [n_bins]
 
     const uint32_t tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
@@ -57,46 +91,43 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_tiles(BinArgs a) {
     const uint64_t n_tiles = (n_pos + kTile - 1) / kTile;
     const uint64_t n_mask = (n_pos + 63) >> 6;
     const uint32_t code_mask = (uint32_t)((1ull << (2 * a.m)) - 1ull);
+    const uint64_t mmask = (1ull << (2 * a.m)) - 1ull;
+    // list slots of this workgroup's current chunk [ch_cur, ch_end) (used by wave 0's last word lane)
+    uint64_t ch_cur = 0, ch_end = 0;
+    uint64_t n_mine = 0;   // pieces found by this workgroup, added to n_superm once at the end
 
     for (uint32_t b = tid; b < a.n_bins; b += kBinBlock) bin_cnt[b] = 0;
 
+    TileFetch f = tile_fetch(a, blockIdx.x, n_tiles, n_mask);
     for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int64_t P0 = (int64_t)(tile * kTile);
         const uint32_t len = kTile + w;   // ranks R[i] for positions P0-1+i
-        // 1. ranks: every thread rolls the canonical m-mer over its own run of positions
+        // 1. ranks: every thread rolls the canonical m-mer over its own run of
+        //    positions, from the two packed words fetched for it
         {
             const uint32_t i0 = tid * kRankPer;
             const uint32_t i1 = i0 + kRankPer < len ? i0 + kRankPer : len;
-            const uint64_t mmask = (1ull << (2 * a.m)) - 1ull;
-            uint64_t fw = 0, rc = 0, cur = 0, nxt = 0;
-            int64_t q = 0;
+            const int64_t j0 = P0 - 1 + (int64_t)i0;
+            const uint32_t s0 = (uint32_t)(j0 & 31);
+            uint64_t fw = 0, rc = 0;
+            if (i0 < i1) {
+                const uint64_t win = s0 ? ((f.w0 << (2 * s0)) | (f.w1 >> (64 - 2 * s0))) : f.w0;
+                fw = win >> (64 - 2 * a.m);
+                rc = revcomp32(win) & mmask;
+            }
             for (uint32_t i = i0; i < i1; i++) {
                 const int64_t j = P0 - 1 + (int64_t)i;
-                if (j >= (int64_t)n_pos) {
-                    R[i] = 0xFFFFFFFFu;
-                    continue;
-                }
-                if (i == i0) {
-                    const uint64_t win = window32(a.packed, j);
-                    fw = win >> (64 - 2 * a.m);
-                    rc = revcomp32(win) & mmask;
-                    q = (j + a.m) >> 5;            // word of the next base to enter
-                    cur = a.packed[q];
-                    nxt = a.packed[q + 1];         // j < n_pos: q + 1 <= n_words + 1, a padded word
-                } else {
-                    const int64_t x = j + a.m - 1;  // the base that enters the m-mer
-                    if ((x >> 5) != q) {
-                        q += 1;
-                        cur = nxt;
-                        nxt = a.packed[q + 1];
-                    }
-                    const uint64_t b2 = (cur >> (62 - 2 * (x & 31))) & 3ull;
+                if (i > i0) {
+                    const uint64_t b2 = pair_base(f.w0, f.w1, s0 + (i - i0) + a.m - 1);
                     fw = ((fw << 2) | b2) & mmask;
                     rc = (rc >> 2) | ((3ull - b2) << (2 * a.m - 2));
                 }
-                R[i] = rank_of(fw, rc, a.m, a.order);
+                R[i] = j < (int64_t)n_pos ? rank_of(fw, rc, a.m, a.order) : 0xFFFFFFFFu;
             }
+            if (tid < kWordsPerTile) okS[tid] = f.ok;
         }
+        // the next tile's loads are in flight while this one is processed
+        f = tile_fetch(a, tile + gridDim.x, n_tiles, n_mask);
         __syncthreads();
         // 2. minimizer of the k-mer at P0-1+i = min R[i .. i+w): each thread takes
         //    a run of kMinPer positions; their windows share the middle part.
@@ -138,11 +169,11 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_tiles(BinArgs a) {
             }
         }
         __syncthreads();
-        // 3. super-mer starts and ends (ballot per 64 positions)
+        // 3. super-mer starts and ends (ballot per 64 positions); the first
+        //    position of a tile always starts a piece (the tile cut)
         for (uint32_t c = wave; c < kWordsPerTile; c += kBinBlock / 64) {
-            uint64_t q = (uint64_t)(P0 >> 6) + c;
-            uint64_t okw = q < n_mask ? a.kmer_ok[q] : 0ull;
-            uint64_t okprev = (c == 0) ? 0ull : ((q - 1) < n_mask ? a.kmer_ok[q - 1] : 0ull);
+            const uint64_t okw = okS[c];
+            const uint64_t okprev = c ? okS[c - 1] : 0ull;
             bool ok = (okw >> lane) & 1ull;
             bool ok_before = lane ? ((okw >> (lane - 1)) & 1ull) : ((okprev >> 63) & 1ull);
             uint32_t t = c * 64 + lane;   // position P0 + t, minimizer M[t+1]
@@ -152,6 +183,10 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_tiles(BinArgs a) {
             if (lane == 0) { stw[c] = sb; brk[c] = bb; }
         }
         __syncthreads();
+        // list slots for this tile's pieces: the rest of the workgroup's
+        // chunk first, then a new chunk (reserved only when the current one
+        // runs out), so only the unused end of a workgroup's last chunk is
+        // left as a hole
         if (wave == 0) {
             uint32_t n = lane < kWordsPerTile ? (uint32_t)__popcll(stw[lane]) : 0u;
             uint32_t incl = n;
@@ -162,7 +197,22 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_tiles(BinArgs a) {
             if (lane < kWordsPerTile) wpre[lane] = incl - n;
             if (lane == kWordsPerTile - 1) {
                 wpre[kWordsPerTile] = incl;
-                tile_base = incl ? add_dev(a.n_superm, (uint64_t)incl) : 0ull;
+                const uint64_t rem = ch_end - ch_cur;
+                uint64_t b1 = ch_cur, sp = incl, b2 = 0;
+                if (incl > rem) {
+                    const uint64_t need = incl - rem;
+                    const uint64_t take = need > kListChunk ? need : kListChunk;
+                    b2 = add_dev(a.list_used, take);
+                    sp = rem;
+                    ch_cur = b2 + need;
+                    ch_end = b2 + take;
+                } else {
+                    ch_cur += incl;
+                }
+                n_mine += incl;
+                tile_base = b1;
+                tile_split = sp;
+                tile_base2 = b2;
             }
         }
         __syncthreads();
@@ -186,8 +236,8 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_tiles(BinArgs a) {
             uint32_t code = mr & code_mask;
             uint32_t bin = a.bin_map ? a.bin_map[code] : (mr % a.n_bins);
             if (bin >= a.n_bins) bin = a.n_bins - 1;   // defensive: a bad map must not index out of range
-            uint64_t idx = tile_base + rank;
-            if (idx < a.cap) {
+            const uint64_t idx = rank < tile_split ? tile_base + rank : tile_base2 + (rank - tile_split);
+            if (idx < a.list_cap) {
                 a.list_desc[idx] = ((uint64_t)(P0 + t) << 24) | nk;
                 a.list_bin[idx] = bin;
                 atomicAdd(&bin_cnt[bin], 1u);
@@ -196,6 +246,13 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_tiles(BinArgs a) {
             }
         }
         __syncthreads();
+    }
+    // the unused end of the last chunk is a hole
+    if (wave == 0) {
+        const uint64_t lo = __shfl(ch_cur, (int)kWordsPerTile - 1), hi = __shfl(ch_end, (int)kWordsPerTile - 1);
+        for (uint64_t i = lo + lane; i < hi; i += 64)
+            if (i < a.list_cap) a.list_bin[i] = kHole;
+        if (lane == kWordsPerTile - 1 && n_mine) add_dev(a.n_superm, n_mine);
     }
     __syncthreads();
     for (uint32_t b = tid; b < a.n_bins; b += kBinBlock)
@@ -243,8 +300,8 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_scatter(BinArgs a) {
     uint32_t* lk = sh + a.n_bins;       // [n_bins] k-mers in this chunk
     uint32_t* gb = sh + 2 * a.n_bins;   // [n_bins] global base of this chunk in the bin
     const uint32_t tid = threadIdx.x;
-    uint64_t n = ld_dev(a.n_superm);
-    if (n > a.cap) n = a.cap;
+    uint64_t n = ld_dev(a.list_used);   // list slots handed out, holes included
+    if (n > a.list_cap) n = a.list_cap;
     const uint64_t chunk = (uint64_t)kBinBlock * kScatterPer;
     for (uint64_t c0 = blockIdx.x * chunk; c0 < n; c0 += (uint64_t)gridDim.x * chunk) {
         for (uint32_t b = tid; b < a.n_bins; b += kBinBlock) { lh[b] = 0; lk[b] = 0; }
@@ -256,10 +313,14 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_scatter(BinArgs a) {
             uint64_t i = c0 + tid + (uint64_t)e * kBinBlock;
             bn[e] = 0xFFFFFFFFu;
             if (i < n) {
-                d[e] = a.list_desc[i];
                 bn[e] = a.list_bin[i];
-                lr[e] = atomicAdd(&lh[bn[e]], 1u);
-                atomicAdd(&lk[bn[e]], (uint32_t)(d[e] & 0xFFFFFFu));
+                if (bn[e] < a.n_bins) {
+                    d[e] = a.list_desc[i];
+                    lr[e] = atomicAdd(&lh[bn[e]], 1u);
+                    atomicAdd(&lk[bn[e]], (uint32_t)(d[e] & 0xFFFFFFu));
+                } else {
+                    bn[e] = 0xFFFFFFFFu;   // a hole
+                }
             }
         }
         __syncthreads();
@@ -289,7 +350,7 @@ hipError_t launch_bin(const BinArgs& a, uint32_t grid, hipStream_t s) {
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     size_t sh_sc = 3 * (size_t)a.n_bins * sizeof(uint32_t);
-    uint64_t chunks = (a.cap + (uint64_t)kBinBlock * kScatterPer - 1) / ((uint64_t)kBinBlock * kScatterPer);
+    uint64_t chunks = (a.list_cap + (uint64_t)kBinBlock * kScatterPer - 1) / ((uint64_t)kBinBlock * kScatterPer);
     uint32_t g = (uint32_t)(chunks < 2048 ? (chunks ? chunks : 1) : 2048);
     hipLaunchKernelGGL(k_bin_scatter, dim3(g), dim3(kBinBlock), sh_sc, s, a);
     return hipGetLastError();

@@ -32,10 +32,11 @@ namespace gerbil {
 __device__ __forceinline__ uint64_t window32(const uint64_t* __restrict__ P, int64_t pos) {
     int64_t q = pos >> 5;  // floor division (arithmetic shift)
     uint32_t r = (uint32_t)(pos & 31);
+    // Both words are read unconditionally (the packed stream has a zero word
+    // before and two after it), so the two loads are in flight together.
     uint64_t a = P[q];
-    if (r == 0) return a;
     uint64_t b = P[q + 1];
-    return (a << (2 * r)) | (b >> (64 - 2 * r));
+    return r ? ((a << (2 * r)) | (b >> (64 - 2 * r))) : a;
 }
 
 // Reverse complement of 32 packed bases: reverse the order of the 2-bit

@@ -8,8 +8,8 @@
 //   pack         16 ASCII bytes per lane -> 32 bits of packed codes and 16
 //                validity bits (SWAR over 4 bytes per 32-bit word);
 //   kmer_ok      bit p = window [p, p+k) is valid, from the "position i and
-//                i+1 belong to one read and are both valid" bitmap by
-//                doubling ANDs (log2 k steps per 64 positions).
+//                i+1 belong to one read and are both valid" bitmap: each
+//                (rare) zero of that bitmap clears the windows that span it.
 #include "common.h"
 #include "internal.h"
 
@@ -138,73 +138,69 @@ __device__ __forceinline__ uint64_t ld_or_zero(const uint64_t* __restrict__ a, u
     return a[i < n ? i : n];
 }
 
-constexpr int kOkWords = 6;  // 64 output bits + up to 255 following bits, plus one word for funnel shifts
-
-// dst[i] = bits of the multiword value src shifted down by s (bit p <- bit p+s), 0 <= s < 128.
-__device__ __forceinline__ void shr_words(const uint64_t (&src)[kOkWords], uint32_t s, uint64_t (&dst)[kOkWords]) {
-    uint32_t o = s >> 6, b = s & 63;
-#pragma unroll
-    for (int i = 0; i < kOkWords; i++) {
-        uint64_t lo0 = (i + 0 < kOkWords) ? src[i] : 0, lo1 = (i + 1 < kOkWords) ? src[i + 1] : 0;
-        uint64_t hi0 = (i + 1 < kOkWords) ? src[i + 1] : 0, hi1 = (i + 2 < kOkWords) ? src[i + 2] : 0;
-        uint64_t lo = o ? lo1 : lo0;   // word i + o
-        uint64_t hi = o ? hi1 : hi0;   // word i + o + 1
-        dst[i] = b ? ((lo >> b) | (hi << (64 - b))) : lo;
-    }
-}
+constexpr int kOkWords = 5;  // 64 output bits + up to 255 following bits
 
 // Thread q computes bitmap word q: bit p = AND of G[p .. p+k-2], where
 // G[i] = valid[i] & valid[i+1] & !read_start[i+1] (i and i+1 are consecutive
-// bases of one read). For k = 1 the bitmap is just `valid`.
-__global__ void k_kmer_ok(const uint64_t* __restrict__ valid, const uint64_t* __restrict__ rs, uint64_t n_mask,
-                          uint32_t k, uint64_t* __restrict__ ok, uint64_t* n_valid) {
-    uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-    uint32_t cnt = 0;
-    if (q < n_mask) {
+// bases of one read). For k = 1 the bitmap is just `valid`. Zeros of G are
+// rare (read ends and undetermined bases), so instead of ANDing shifted
+// copies the thread walks the zeros of G in [64q, 64q + 63 + k - 2] and
+// clears, for each zero z, the windows p in [z - k + 2, z] of its word.
+__global__ void __launch_bounds__(256) k_kmer_ok(const uint64_t* __restrict__ valid, const uint64_t* __restrict__ rs,
+                                                 uint64_t n_mask, uint32_t k, uint64_t* __restrict__ ok,
+                                                 uint64_t* n_valid) {
+    __shared__ uint32_t wsum[4];
+    uint64_t cnt = 0;
+    for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < n_mask;
+         q += (uint64_t)gridDim.x * blockDim.x) {
         uint64_t res;
         if (k == 1) {
             res = valid[q];
         } else {
-            uint64_t V[kOkWords + 1], R[kOkWords + 1], A[kOkWords], B[kOkWords];
+            const uint32_t span = k - 2;                    // window p needs G[p .. p+span]
+            const uint32_t nw = (63 + span) / 64 + 1;       // words of G that can hold such zeros (<= 5)
+            uint64_t V[kOkWords + 1], R[kOkWords + 1];
 #pragma unroll
             for (int i = 0; i <= kOkWords; i++) {
                 V[i] = ld_or_zero(valid, q + i, n_mask);
                 R[i] = ld_or_zero(rs, q + i, n_mask);
             }
+            res = ~0ull;
 #pragma unroll
             for (int i = 0; i < kOkWords; i++) {
-                uint64_t vnext = (V[i] >> 1) | (V[i + 1] << 63);
-                uint64_t rnext = (R[i] >> 1) | (R[i + 1] << 63);
-                A[i] = V[i] & vnext & ~rnext;
-            }
-            // A holds ANDs over spans of s bits; double s while 2s <= k-1.
-            uint32_t span = 1;
-#pragma unroll
-            for (int lvl = 0; lvl < 7; lvl++) {
-                if (2 * span <= k - 1) {
-                    shr_words(A, span, B);
-#pragma unroll
-                    for (int i = 0; i < kOkWords; i++) A[i] &= B[i];
-                    span *= 2;
+                if ((uint32_t)i >= nw) break;
+                const uint64_t vnext = (V[i] >> 1) | (V[i + 1] << 63);
+                const uint64_t rnext = (R[i] >> 1) | (R[i + 1] << 63);
+                uint64_t zeros = ~(V[i] & vnext & ~rnext);
+                while (zeros) {
+                    const uint32_t z = 64u * (uint32_t)i + (uint32_t)__builtin_ctzll(zeros);   // relative to 64q
+                    zeros &= zeros - 1;
+                    if (z > 63u + span) break;                      // beyond the last window of this word
+                    const uint32_t lo = z > span ? z - span : 0u;   // windows [lo, hi] contain z
+                    const uint32_t hi = z < 63u ? z : 63u;
+                    if (lo <= hi) res &= ~((~0ull >> (63u - hi)) & (~0ull << lo));
                 }
             }
-            shr_words(A, (k - 1) - span, B);   // (k-1) - span < span <= 128
-            res = A[0] & B[0];
         }
         ok[q] = res;
-        cnt = __popcll(res);
+        cnt += __popcll(res);
     }
-    // one atomic per wave
-    uint32_t tot = cnt;
+    // one atomic per workgroup (a single counter takes every add in turn)
+    uint32_t tot = (uint32_t)cnt;
     for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
-    if (__lane_id() == 0 && tot) add_dev(n_valid, (uint64_t)tot);
+    if (__lane_id() == 0) wsum[threadIdx.x >> 6] = tot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint64_t t = (uint64_t)wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        if (t) add_dev(n_valid, t);
+    }
 }
 
 hipError_t launch_kmer_ok(const uint64_t* valid, const uint64_t* read_start, uint64_t n_mask, uint32_t k,
                           uint64_t* kmer_ok, uint64_t* n_valid, hipStream_t s) {
-    uint64_t g = (n_mask + 255) / 256;
-    if (g == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_kmer_ok, dim3((uint32_t)g), dim3(256), 0, s, valid, read_start, n_mask, k, kmer_ok, n_valid);
+    if (n_mask == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_kmer_ok, dim3(grid_for(n_mask, 256, 4096)), dim3(256), 0, s, valid, read_start, n_mask, k,
+                       kmer_ok, n_valid);
     return hipGetLastError();
 }
 

@@ -27,9 +27,11 @@ struct BinArgs {
     uint64_t n_bytes;
     uint32_t k, m, n_bins, order;
     const uint32_t* bin_map;
-    uint64_t cap;
-    uint64_t* list_desc;    // [cap] tile order
-    uint32_t* list_bin;     // [cap]
+    uint64_t cap;           // descriptors (super-mer pieces) that fit in desc
+    uint64_t list_cap;      // cap + kListSlack: slots of the tile-order list, holes included
+    uint64_t* list_desc;    // [list_cap] tile order
+    uint32_t* list_bin;     // [list_cap] bin, or kHole for a slot left unused
+    uint64_t* list_used;    // scalar: list slots handed out
     uint64_t* n_superm;     // scalar
     uint32_t* bin_count;    // [n_bins] super-mers per bin
     uint32_t* bin_fill;     // [n_bins] scatter cursors
@@ -39,6 +41,14 @@ struct BinArgs {
     uint32_t* status;
 };
 hipError_t launch_bin(const BinArgs& a, uint32_t grid, hipStream_t s);
+// The tile kernel hands out list slots to each workgroup in chunks of at
+// least kListChunk and fills them without gaps; only the unused end of each
+// workgroup's last chunk (under kListChunk slots) is a hole. At most
+// kMaxTileGrid workgroups, hence the slack.
+constexpr uint32_t kListChunk = 2048;
+constexpr uint32_t kMaxTileGrid = 2048;
+constexpr uint64_t kListSlack = (uint64_t)kListChunk * kMaxTileGrid;
+constexpr uint32_t kHole = 0xFFFFFFFFu;
 
 // ------------------------------------------------------------ count
 struct Table {

@@ -556,9 +556,13 @@ __device__ __forceinline__ bool lds_insert(uint64_t* w0, uint64_t* rest, uint32_
     }
 }
 
-// Keys loaded per thread before they are inserted (independent loads in flight).
+// Keys loaded per thread before they are inserted (independent loads in
+// flight): enough that a sub-table filled to its default target (0.8 of the
+// slots) is loaded in one batch.
 template <int W>
-struct TableBatch { static constexpr int K = W <= 2 ? 8 : W <= 4 ? 4 : W == 5 ? 2 : 1; };
+struct TableBatch {
+    static constexpr int K = W == 1 ? 12 : W == 2 ? 7 : W == 3 ? 5 : W == 4 ? 4 : W <= 7 ? 3 : 2;
+};
 
 // Stage D: count one sub-table in LDS, then dump it.
 template <int W>
@@ -602,20 +606,23 @@ __device__ void stage_table(const CountArgs& a, const LdsArgs& l, const Lds& s, 
         }
     }
     __syncthreads();
-    // dump: count this thread's pairs, one reservation for the block, write
+    // dump: count this thread's pairs, one reservation for the block (its
+    // round trip overlaps the histogram), write
     uint32_t mine = 0;
+    for (uint32_t sl = tid; sl < C; sl += kLdsBlock) mine += cnt[sl] >= a.threshold;
+    uint32_t total;
+    const uint32_t pre = block_excl_scan(mine, wsum, total);
+    uint64_t base = 0;
+    if (tid == 0 && total) base = add_dev(a.n_out, (uint64_t)total);
     for (uint32_t sl = tid; sl < C; sl += kLdsBlock) {
         const uint32_t c = cnt[sl];
         if (c) {
             if (c < kLdsHist) atomicAdd(&s.hist[c], 1u);
             else add_dev(&a.hist[c < kHistInternal - 1 ? c : kHistInternal - 1], 1ull);
             wmax = c > wmax ? c : wmax;
-            mine += c >= a.threshold;
         }
     }
-    uint32_t total;
-    const uint32_t pre = block_excl_scan(mine, wsum, total);
-    if (tid == 0) *s_base = total ? add_dev(a.n_out, (uint64_t)total) : 0ull;
+    if (tid == 0) *s_base = base;
     __syncthreads();
     uint64_t pos = *s_base + pre;
     for (uint32_t sl = tid; sl < C && mine; sl += kLdsBlock) {
@@ -657,34 +664,67 @@ __device__ __forceinline__ void hist_end(const CountArgs& a, const Lds& s, uint3
         if (s.hist[b]) add_dev(&a.hist[b], (uint64_t)s.hist[b]);
 }
 
-// BATCHED: every stage of every rank from one queue.
+// Segment of queue item `item` (last j < ns with start[j] <= item) and its
+// first item, searched by the 64 lanes of one wave from `hint`: one
+// coalesced load of 64 segment starts per step. Items a workgroup pops
+// increase, so start[hint] <= item and the answer is at most a few segments on.
+__device__ __forceinline__ uint32_t locate_item(const uint64_t* start, uint32_t ns, uint64_t item, uint32_t hint,
+                                                uint64_t& first) {
+    const uint32_t lane = __lane_id();
+    for (;;) {
+        const uint32_t j = hint + lane;
+        const uint64_t v = j < ns ? start[j] : ~0ull;
+        const uint64_t m = __ballot(v <= item);   // a prefix of the lanes (starts never decrease)
+        if (m != ~0ull) {
+            const uint32_t h = m ? 63u - (uint32_t)__clzll(m) : 0u;
+            first = __shfl(v, (int)h);
+            return hint + h;
+        }
+        hint += 63;
+    }
+}
+
+// BATCHED: every stage of every rank from one queue. Wave 0 pops the next
+// item as soon as the current one starts, so the queue's round trip and the
+// segment search overlap with the stage's work. Dependencies point to earlier
+// items only, and the earliest unfinished item is always some workgroup's
+// current one, so holding one popped item ahead cannot deadlock.
 template <int W>
 __global__ void __launch_bounds__(kLdsBlock) k_lds_persistent(CountArgs a, LdsArgs l) {
     extern __shared__ __align__(16) uint8_t lds_raw[];
     const Lds s = lds_carve(lds_raw);
     uint64_t* s_item = (uint64_t*)(lds_raw + kLdsHist * 4);
-    uint32_t* s_seg = (uint32_t*)(s_item + 1);
+    uint64_t* s_first = s_item + 1;
+    uint32_t* s_seg = (uint32_t*)(s_item + 2);
+    static_assert(kLdsHist * 4 + 24 <= kLdsReserved, "queue scalars exceed the reserved LDS");
     const uint32_t tid = threadIdx.x;
-    if (tid == 0) *s_seg = 0;
     hist_begin(s);
     uint32_t wmax = 0;
     const uint32_t ns = *l.n_seg;
     const uint64_t total = l.seg_start[ns];
     const uint32_t L = l.lag;
-    for (;;) {
+    if (tid < 64) {
+        uint64_t it = 0, first = 0;
+        if (tid == 0) it = add_dev(l.cursor, 1ull);
+        it = __shfl(it, 0);
+        const uint32_t sg = it < total ? locate_item(l.seg_start, ns, it, 0, first) : 0u;
         if (tid == 0) {
-            uint64_t item = add_dev(l.cursor, 1ull);
-            *s_item = item;
-            if (item < total) *s_seg = find_segment(l.seg_start, ns, item, *s_seg);
+            *s_item = it;
+            *s_first = first;
+            *s_seg = sg;
         }
-        __syncthreads();
+    }
+    __syncthreads();
+    for (;;) {
         const uint64_t item = *s_item;
         if (item >= total) break;
         const uint32_t seg = *s_seg;
+        const uint32_t local = (uint32_t)(item - *s_first);
+        uint64_t nxt = 0;
+        if (tid == 0) nxt = add_dev(l.cursor, 1ull);   // waited for only after the stage
         const uint32_t st = seg & 3, tick = seg >> 2;
         const uint32_t lagv = st == 0 ? 0u : st == 1 ? 1u : st == 2 ? 2u : 2u + L;
         const uint32_t r = tick - lagv;
-        const uint32_t local = (uint32_t)(item - l.seg_start[seg]);
         if (tid == 0) {
             if (st == 1) wait_done(l.done + 4 * r + 0, l.rank_nchunk[r], kLdsWait, a.status, ST_SPIN);
             if (st == 2) {
@@ -696,10 +736,30 @@ __global__ void __launch_bounds__(kLdsBlock) k_lds_persistent(CountArgs a, LdsAr
         __syncthreads();
         const uint64_t t0 = l.stage_clocks ? wall_clock64() : 0;
         run_stage<W>(a, l, s, st, r, local, wmax);
-        signal_done(l.done + 4 * r + st);
+        // Stages 0-2 publish data that later stages read, so their stores are
+        // drained first. The table stage only releases its key slot: its key
+        // loads have completed (their values were inserted), and its output
+        // stores are read by no other stage, so it signals without a drain.
+        if (st == 3) {
+            __syncthreads();
+            if (tid == 0) __hip_atomic_fetch_add(l.done + 4 * r + st, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            signal_done(l.done + 4 * r + st);
+        }
+        // (either way a barrier: every thread has read this item's scalars)
         if (l.stage_clocks && tid == 0) {
             add_dev(&l.stage_clocks[st], wall_clock64() - t0);
             add_dev(&l.stage_clocks[4 + st], 1ull);
+        }
+        if (tid < 64) {
+            uint64_t first = 0;
+            const uint64_t it = __shfl(nxt, 0);
+            const uint32_t sg = it < total ? locate_item(l.seg_start, ns, it, seg, first) : seg;
+            if (tid == 0) {
+                *s_item = it;
+                *s_first = first;
+                *s_seg = sg;
+            }
         }
         __syncthreads();
     }
