@@ -234,11 +234,12 @@ def main(argv=None):
             shared_out.update(cap=job.cap, keys=job.keys_d, counts=job.counts_d)
             for _ in range(args.warmup):
                 job.run()
-            res = job.result()
+            if args.warmup:
+                job.result()   # raises if a warm-up run hit a capacity or device error
             if graph:
                 job.capture()
                 job.replay()
-                res = job.result()
+                job.result()
             torch.cuda.synchronize()
             step_ms = []
             starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]

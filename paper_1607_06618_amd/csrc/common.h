@@ -89,13 +89,18 @@ __device__ __forceinline__ uint64_t fmix64(uint64_t z) {
     return z;
 }
 
-// Hash of a key: multiplicative combine of the words, then an avalanche.
-// Only slot positions depend on it, never results.
+// Hash of a key: the words folded by XOR at distinct rotations, then one
+// avalanche (two 64-bit multiplies in all; a 64-bit multiply costs four
+// quarter-rate 32-bit multiplies on this GPU, and every k-mer is hashed
+// twice). Only slot positions depend on it, never results.
 template <int W>
 __device__ __forceinline__ uint64_t key_hash(const uint64_t (&key)[W], uint64_t seed) {
-    uint64_t h = seed;
+    uint64_t h = seed ^ key[0];
 #pragma unroll
-    for (int i = 0; i < W; i++) h = (h ^ key[i]) * 0x9E3779B97F4A7C15ull;
+    for (int i = 1; i < W; i++) {
+        const int r = (23 * i) & 63;
+        h ^= (key[i] << r) | (key[i] >> ((64 - r) & 63));
+    }
     return fmix64(h);
 }
 

@@ -158,7 +158,7 @@ struct LdsArgs {
     uint32_t* sp_cnt;         // [sp_cap] keys per sub-table
     uint64_t* sp_off;         // [sp_cap] first key of a sub-table inside its key slot
     uint32_t* sp_cur;         // [sp_cap] scatter cursors
-    uint64_t* keys;           // Q key slots of slot_keys keys (W words each)
+    uint64_t* keys;           // Q key slots of slot_keys keys, word-major: word w of key i at w * slot_keys + i
     uint64_t slot_keys;
     uint32_t Q, lag;
     uint32_t target;          // keys per sub-table

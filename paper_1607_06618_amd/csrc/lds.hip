@@ -491,7 +491,7 @@ __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s
             const uint64_t gpos = (uint64_t)dst[lo] + (i - lp[lo]);
             if (gpos < l.slot_keys) {
 #pragma unroll
-                for (int w = 0; w < W; w++) st_dev(&slot[gpos * W + w], buf[(uint64_t)i * W + w]);
+                for (int w = 0; w < W; w++) st_dev(&slot[(uint64_t)w * l.slot_keys + gpos], buf[(uint64_t)i * W + w]);
             } else {
                 set_status(a.status, ST_POOL);
             }
@@ -579,7 +579,9 @@ __device__ void stage_table(const CountArgs& a, const LdsArgs& l, const Lds& s, 
     const uint64_t sb = l.rank_spbase[r];
     const uint64_t n = ld_dev(&l.sp_cnt[sb + j]);
     const uint64_t off = ld_dev(&l.sp_off[sb + j]);
-    const uint64_t* keys = l.keys + (uint64_t)(r % l.Q) * l.slot_keys * W + off * W;
+    // the slot holds its keys word-major (word w of run position i at
+    // w * slot_keys + i), so each word of a batch is one coalesced load per wave
+    const uint64_t* keys = l.keys + (uint64_t)(r % l.Q) * l.slot_keys * W + off;
     for (uint32_t i = tid; i < C; i += kLdsBlock) {
         w0[i] = GERBIL_EMPTY;
         cnt[i] = 0;
@@ -593,7 +595,7 @@ __device__ void stage_table(const CountArgs& a, const LdsArgs& l, const Lds& s, 
             const uint64_t i = base + (uint64_t)e * kLdsBlock + tid;
             if (i < lim) {
 #pragma unroll
-                for (int w = 0; w < W; w++) key[e][w] = ld_dev(&keys[i * W + w]);
+                for (int w = 0; w < W; w++) key[e][w] = ld_dev(&keys[(uint64_t)w * l.slot_keys + i]);
             }
         }
 #pragma unroll
