@@ -332,7 +332,9 @@ int32_t count_lds(const gerbil_bins* bins, const gerbil_params* p, void* ws, uin
     LdsLayout LL;
     const uint64_t fixed = fixed0 + lds_fixed(z, ws, fixed0, &LL);
     if (fixed + kAlign > ws_bytes) return GERBIL_EINVAL;
-    uint64_t slot_keys = (ws_bytes - fixed - kAlign) / ((uint64_t)z.Q * 8ull * W);
+    const uint64_t key_bytes = 8ull * (W - 1) + tail_bytes_for(p->k);
+    uint64_t slot_keys = (ws_bytes - fixed - kAlign) / ((uint64_t)z.Q * key_bytes);
+    while (slot_keys && (uint64_t)z.Q * slot_words_for(slot_keys, p->k) * 8ull > ws_bytes - fixed - kAlign) slot_keys--;
     if (slot_keys < 1) return GERBIL_EINVAL;
     if (slot_keys > 0xFFFFFFFFull) slot_keys = 0xFFFFFFFFull;   // run offsets are 32-bit inside a slot
     fill_state(state, p, bins, cap, ovf_cap, L);
@@ -355,6 +357,8 @@ int32_t count_lds(const gerbil_bins* bins, const gerbil_params* p, void* ws, uin
     l.sp_cur = LL.sp_cur;
     l.keys = LL.keys;
     l.slot_keys = slot_keys;
+    l.slot_words = slot_words_for(slot_keys, p->k);
+    l.tail_bytes = tail_bytes_for(p->k);
     l.Q = z.Q;
     l.lag = z.lag;
     l.target = z.target;
@@ -518,9 +522,9 @@ int32_t gerbil_bin(const gerbil_encoded* enc, const gerbil_params* p, void* ws, 
     hipError_t e = launch_fill_u64(L.scalars, 4, 0, stream);
     if (e == hipSuccess) e = launch_fill_u32(L.bin_count, p->n_bins, 0, stream);
     uint64_t n_tiles = (enc->n_bytes + kTile - 1) / kTile;
-    uint64_t g = std::min<uint64_t>(std::max<uint64_t>(n_tiles, 1), (uint64_t)device_cus() * 8);
+    uint64_t g = std::max<uint64_t>(n_tiles, 1);
     if (g > kMaxTileGrid) g = kMaxTileGrid;   // bounds the list's slack (one partial chunk per workgroup)
-    if (e == hipSuccess) e = launch_bin(a, (uint32_t)g, stream);
+    if (e == hipSuccess) e = launch_bin(a, (uint32_t)g, (uint32_t)device_cus(), stream);
     return hip_status(e);
 }
 
@@ -541,7 +545,7 @@ int32_t gerbil_count_workspace(const gerbil_bins* bins, const gerbil_params* p, 
         LdsSizing z = lds_sizing(p, bins->n_bytes);
         uint64_t fixed = count_fixed(W, ovf_capacity(p), p->n_bins, false, nullptr, nullptr);
         fixed += lds_fixed(z, nullptr, 0, nullptr);
-        *bytes = fixed + (uint64_t)z.Q * lds_slot_keys(mx, z) * 8ull * W + kAlign;
+        *bytes = fixed + (uint64_t)z.Q * slot_words_for(lds_slot_keys(mx, z), p->k) * 8ull + kAlign;
         return GERBIL_OK;
     }
     const uint64_t slots = slots_for(mx, load_of(p));

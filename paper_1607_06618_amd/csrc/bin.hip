@@ -46,6 +46,21 @@ constexpr uint32_t kMinPer = (kTile + 1 + kBinBlock - 1) / kBinBlock;      // mi
 static_assert(31 + kRankPer - 1 + 15 <= 64, "a rank run must fit in two packed words");
 static_assert(kWordsPerTile <= kBinBlock, "one bitmap word per thread");
 
+// Position of the n-th (from 0) set bit of x; x has more than n set bits.
+__device__ __forceinline__ uint32_t select_bit(uint64_t x, uint32_t n) {
+    uint32_t pos = 0;
+#pragma unroll
+    for (uint32_t s = 32; s >= 1; s >>= 1) {
+        const uint32_t c = (uint32_t)__popcll(x & ((1ull << s) - 1ull));
+        if (n >= c) {
+            n -= c;
+            x >>= s;
+            pos += s;
+        }
+    }
+    return pos;
+}
+
 // Global data one tile needs, loaded one tile ahead into registers.
 struct TileFetch {
     uint64_t w0, w1;   // the two packed words of this thread's rank run
@@ -75,7 +90,7 @@ __device__ __forceinline__ uint64_t pair_base(uint64_t w0, uint64_t w1, uint32_t
     return (w >> (62 - 2 * (o & 31))) & 3ull;
 }
 
-__global__ void __launch_bounds__(kBinBlock) k_bin_tiles(BinArgs a) {
+__global__ void __launch_bounds__(kBinBlock, 7) k_bin_tiles(BinArgs a) {
     __shared__ uint32_t R[kRankLen];
     __shared__ uint32_t M[kTile + 1];
     __shared__ uint64_t brk[kWordsPerTile];
@@ -144,6 +159,7 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_tiles(BinArgs a) {
                 } else {
                     // window [i, i+w) = [i, i1-1) + [i1-1, i0+w) + [i0+w, i+w)
                     uint32_t mid = 0xFFFFFFFFu;
+#pragma unroll 8
                     for (uint32_t t = i1 - 1; t < i0 + w; t++) mid = min(mid, R[t]);
                     uint32_t suf[kMinPer], pre[kMinPer];
                     uint32_t run = 0xFFFFFFFFu;
@@ -216,13 +232,19 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_tiles(BinArgs a) {
             }
         }
         __syncthreads();
-        // 4. one descriptor per start
-        for (uint32_t c = wave; c < kWordsPerTile; c += kBinBlock / 64) {
-            uint64_t sw = stw[c];
-            if (!((sw >> lane) & 1ull)) continue;
-            uint32_t t = c * 64 + lane;
-            uint32_t rank = wpre[c] + (uint32_t)__popcll(sw & ((1ull << lane) - 1ull));
-            uint64_t above = (lane == 63) ? 0ull : (brk[c] & ~((2ull << lane) - 1ull));
+        // 4. one descriptor per start: thread i takes starts i, i + kBinBlock, ...
+        //    of the tile, so the lanes stay busy however sparse the starts are
+        const uint32_t n_st = wpre[kWordsPerTile];
+        for (uint32_t q = tid; q < n_st; q += kBinBlock) {
+            uint32_t lo = 0, hi = kWordsPerTile;   // word of start q: last c with wpre[c] <= q
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (wpre[mid] <= q) lo = mid; else hi = mid;
+            }
+            const uint32_t c = lo;
+            const uint32_t bit = select_bit(stw[c], q - wpre[c]);
+            const uint32_t t = c * 64 + bit;
+            const uint64_t above = (bit == 63) ? 0ull : (brk[c] & ~((2ull << bit) - 1ull));
             uint32_t end = kTile;
             if (above) {
                 end = c * 64 + (uint32_t)__builtin_ctzll(above);
@@ -231,12 +253,12 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_tiles(BinArgs a) {
                     if (brk[d]) { end = d * 64 + (uint32_t)__builtin_ctzll(brk[d]); break; }
                 }
             }
-            uint32_t nk = end - t;
-            uint32_t mr = M[t + 1];
-            uint32_t code = mr & code_mask;
+            const uint32_t nk = end - t;
+            const uint32_t mr = M[t + 1];
+            const uint32_t code = mr & code_mask;
             uint32_t bin = a.bin_map ? a.bin_map[code] : (mr % a.n_bins);
             if (bin >= a.n_bins) bin = a.n_bins - 1;   // defensive: a bad map must not index out of range
-            const uint64_t idx = rank < tile_split ? tile_base + rank : tile_base2 + (rank - tile_split);
+            const uint64_t idx = q < tile_split ? tile_base + q : tile_base2 + (q - tile_split);
             if (idx < a.list_cap) {
                 a.list_desc[idx] = ((uint64_t)(P0 + t) << 24) | nk;
                 a.list_bin[idx] = bin;
@@ -341,9 +363,18 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_scatter(BinArgs a) {
     }
 }
 
-hipError_t launch_bin(const BinArgs& a, uint32_t grid, hipStream_t s) {
+hipError_t launch_bin(const BinArgs& a, uint32_t max_grid, uint32_t cus, hipStream_t s) {
     size_t sh_tiles = (size_t)a.n_bins * sizeof(uint32_t);
-    hipLaunchKernelGGL(k_bin_tiles, dim3(grid), dim3(kBinBlock), sh_tiles, s, a);
+    // as many workgroups as are resident at once (a second, partial wave of
+    // workgroups would double the time of a grid-stride kernel)
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bin_tiles, kBinBlock, sh_tiles) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    uint64_t grid = (uint64_t)cus * (uint32_t)per_cu;
+    if (grid > max_grid) grid = max_grid;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_bin_tiles, dim3((uint32_t)grid), dim3(kBinBlock), sh_tiles, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, a);

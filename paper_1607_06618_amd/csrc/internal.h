@@ -40,7 +40,7 @@ struct BinArgs {
     uint64_t* desc;         // [cap] bin order
     uint32_t* status;
 };
-hipError_t launch_bin(const BinArgs& a, uint32_t grid, hipStream_t s);
+hipError_t launch_bin(const BinArgs& a, uint32_t max_grid, uint32_t cus, hipStream_t s);
 // The tile kernel hands out list slots to each workgroup in chunks of at
 // least kListChunk and fills them without gaps; only the unused end of each
 // workgroup's last chunk (under kListChunk slots) is a hole. At most
@@ -128,7 +128,16 @@ uint32_t persistent_blocks_per_cu(uint32_t W, uint32_t block);
 // LDS sub-table path. A rank is one hash slice of a bin (bins too large for
 // kLdsMaxSub sub-tables are cut into slices by the high hash bits); a rank
 // has P sub-tables, each counted by one workgroup in LDS.
-constexpr uint32_t kLdsBlock = 1024;            // threads per workgroup (one workgroup per CU)
+constexpr uint32_t kLdsBlock = 1024;
+// Bytes that hold the last word of a key: 2 bits per base of its k - 32(W-1) bases.
+inline uint32_t tail_bytes_for(uint32_t k) {
+    const uint32_t W = (k + 31) / 32, r = k - 32 * (W - 1);
+    return r <= 4 ? 1u : r <= 8 ? 2u : r <= 16 ? 4u : 8u;
+}
+inline uint64_t slot_words_for(uint64_t slot_keys, uint32_t k) {
+    const uint32_t W = (k + 31) / 32;
+    return slot_keys * (W - 1) + (slot_keys * tail_bytes_for(k) + 7) / 8;
+}            // threads per workgroup (one workgroup per CU)
 constexpr uint32_t kLdsBytes = 160 * 1024;      // dynamic LDS per workgroup
 constexpr uint32_t kLdsMaxSub = 4096;           // sub-tables per rank (LDS of the scatter stage)
 constexpr uint32_t kLdsReserved = 2048;         // LDS kept for the histogram and scalars
@@ -158,8 +167,13 @@ struct LdsArgs {
     uint32_t* sp_cnt;         // [sp_cap] keys per sub-table
     uint64_t* sp_off;         // [sp_cap] first key of a sub-table inside its key slot
     uint32_t* sp_cur;         // [sp_cap] scatter cursors
-    uint64_t* keys;           // Q key slots of slot_keys keys, word-major: word w of key i at w * slot_keys + i
+    // Q key slots of slot_keys keys each, word-major: word w < W-1 of key i at
+    // w * slot_keys + i (uint64), then the last word of every key in
+    // tail_bytes bytes (1, 2, 4 or 8: it holds only k - 32(W-1) bases).
+    uint64_t* keys;
     uint64_t slot_keys;
+    uint64_t slot_words;      // uint64 words per slot
+    uint32_t tail_bytes;
     uint32_t Q, lag;
     uint32_t target;          // keys per sub-table
     uint32_t table_slots;     // LDS slots per sub-table

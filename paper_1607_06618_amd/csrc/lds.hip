@@ -314,6 +314,40 @@ __device__ __forceinline__ void seg_step(uint32_t k, Segment<W>& g) {
     roll_base<W>(g.fw, g.rc, b, k);
 }
 
+// The last word of key i of a slot, stored in `tb` bytes (device-coherent).
+__device__ __forceinline__ void store_tail(uint8_t* tail, uint64_t i, uint64_t v, uint32_t tb) {
+    switch (tb) {
+        case 1: st_dev(tail + i, (uint8_t)v); break;
+        case 2: st_dev((uint16_t*)tail + i, (uint16_t)v); break;
+        case 4: st_dev((uint32_t*)tail + i, (uint32_t)v); break;
+        default: st_dev((uint64_t*)tail + i, v); break;
+    }
+}
+
+// Last words of K keys (run positions off + ix[e]); one uniform branch on the width.
+template <int K, int W>
+__device__ __forceinline__ void load_tails(const uint8_t* tail, uint64_t off, const uint64_t (&ix)[K], uint32_t tb,
+                                           uint64_t (&key)[K][W]) {
+    switch (tb) {
+        case 1:
+#pragma unroll
+            for (int e = 0; e < K; e++) key[e][W - 1] = ld_dev(tail + off + ix[e]);
+            break;
+        case 2:
+#pragma unroll
+            for (int e = 0; e < K; e++) key[e][W - 1] = ld_dev((const uint16_t*)tail + off + ix[e]);
+            break;
+        case 4:
+#pragma unroll
+            for (int e = 0; e < K; e++) key[e][W - 1] = ld_dev((const uint32_t*)tail + off + ix[e]);
+            break;
+        default:
+#pragma unroll
+            for (int e = 0; e < K; e++) key[e][W - 1] = ld_dev((const uint64_t*)tail + off + ix[e]);
+            break;
+    }
+}
+
 // Exclusive prefix of cnt[0..n) into pre[0..n) by the whole block; returns the total.
 __device__ __forceinline__ uint32_t block_scan_array(const uint32_t* cnt, uint32_t* pre, uint32_t n, uint32_t* wsum) {
     const uint32_t per = (n + kLdsBlock - 1) / kLdsBlock;
@@ -428,7 +462,8 @@ __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s
     const uint32_t tid = threadIdx.x;
     const uint32_t b = l.rank_bin[r], v = l.rank_slice[r], V = l.rank_nslice[r], P = l.rank_nsub[r];
     const uint64_t sb = l.rank_spbase[r];
-    uint64_t* slot = l.keys + (uint64_t)(r % l.Q) * l.slot_keys * W;
+    uint64_t* slot = l.keys + (uint64_t)(r % l.Q) * l.slot_words;
+    uint8_t* tail = (uint8_t*)(slot + (uint64_t)(W - 1) * l.slot_keys);
     const ChunkLds c = chunk_lds(s);
     static_assert(kChunkHeader + 3 * 4 * kLdsMaxSub + (uint64_t)R * 8 * W * kLdsBlock <= kLdsBytes - kLdsReserved,
                   "scatter stage exceeds the LDS budget");
@@ -491,7 +526,8 @@ __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s
             const uint64_t gpos = (uint64_t)dst[lo] + (i - lp[lo]);
             if (gpos < l.slot_keys) {
 #pragma unroll
-                for (int w = 0; w < W; w++) st_dev(&slot[(uint64_t)w * l.slot_keys + gpos], buf[(uint64_t)i * W + w]);
+                for (int w = 0; w + 1 < W; w++) st_dev(&slot[(uint64_t)w * l.slot_keys + gpos], buf[(uint64_t)i * W + w]);
+                store_tail(tail, gpos, buf[(uint64_t)i * W + W - 1], l.tail_bytes);
             } else {
                 set_status(a.status, ST_POOL);
             }
@@ -581,7 +617,8 @@ __device__ void stage_table(const CountArgs& a, const LdsArgs& l, const Lds& s, 
     const uint64_t off = ld_dev(&l.sp_off[sb + j]);
     // the slot holds its keys word-major (word w of run position i at
     // w * slot_keys + i), so each word of a batch is one coalesced load per wave
-    const uint64_t* keys = l.keys + (uint64_t)(r % l.Q) * l.slot_keys * W + off;
+    const uint64_t* keys = l.keys + (uint64_t)(r % l.Q) * l.slot_words + off;
+    const uint8_t* tail = (const uint8_t*)(l.keys + (uint64_t)(r % l.Q) * l.slot_words + (uint64_t)(W - 1) * l.slot_keys);
     for (uint32_t i = tid; i < C; i += kLdsBlock) {
         w0[i] = GERBIL_EMPTY;
         cnt[i] = 0;
@@ -589,15 +626,20 @@ __device__ void stage_table(const CountArgs& a, const LdsArgs& l, const Lds& s, 
     __syncthreads();
     const uint64_t lim = (off + n <= l.slot_keys) ? n : 0;   // a run past the slot was never written
     for (uint64_t base = 0; base < lim; base += (uint64_t)kLdsBlock * K) {
+        // every lane loads K keys (lanes past the run re-read its last key and
+        // drop it), so all loads of the batch are in flight together
         uint64_t key[K][W];
+        uint64_t ix[K];
 #pragma unroll
         for (int e = 0; e < K; e++) {
             const uint64_t i = base + (uint64_t)e * kLdsBlock + tid;
-            if (i < lim) {
-#pragma unroll
-                for (int w = 0; w < W; w++) key[e][w] = ld_dev(&keys[(uint64_t)w * l.slot_keys + i]);
-            }
+            ix[e] = i < lim ? i : lim - 1;
         }
+#pragma unroll
+        for (int e = 0; e < K; e++)
+#pragma unroll
+            for (int w = 0; w + 1 < W; w++) key[e][w] = ld_dev(&keys[(uint64_t)w * l.slot_keys + ix[e]]);
+        load_tails<K, W>(tail, off, ix, l.tail_bytes, key);
 #pragma unroll
         for (int e = 0; e < K; e++) {
             const uint64_t i = base + (uint64_t)e * kLdsBlock + tid;
