@@ -326,7 +326,8 @@ def main(argv=None):
         "config": {"workload": w.name, "description": w.note, "k": w.k, "m": w.m, "n_bins": w.n_bins,
                    "threshold": w.threshold, "reads": int(offsets.size - 1), "bytes": int(ascii_.size),
                    "valid_windows": int(n_valid), "super_mers": int(rep.n_superm), "distinct": n_distinct,
-                   "pairs_out": int(rep.n_out), "schedule": head, "table": head_table},
+                   "pairs_out": int(rep.n_out), "emergency_keys": int(rep.n_overflow), "schedule": head,
+                   "table": head_table},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "p50_ms": percentile(R["step_ms"], 50), "p99_ms": percentile(R["step_ms"], 99),

@@ -108,6 +108,12 @@ typedef struct {
                                 units of the 100 MHz wall clock) of the four LDS stages (count,
                                 scan, scatter, table) in [0..3] and their item counts in [4..7];
                                 NULL = none                                                       */
+    uint32_t size_sample;    /* LDS tables: sub-table runs are sized from a sample, every
+                                size_sample-th segment of 32/size_sample k-mers (a run holds
+                                size_sample x its sampled keys plus a four-sigma margin; if a run
+                                still overflows, all of its keys take the emergency area, so
+                                results stay exact); 1 = count every k-mer; 0 = default 8       */
+    uint32_t reserved0;
 } gerbil_params;
 
 /* Output of gerbil_encode. All pointers point into the encode workspace. */

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <vector>
 
 #include "../../include/gerbil.h"
@@ -193,9 +194,11 @@ constexpr uint32_t kDefaultLdsTheta = 64;   // single-slot probes are cheap in L
 constexpr double kDefaultLdsFill = 0.8;     // k-mers per LDS slot (distinct keys are fewer)
 
 struct LdsSizing {
-    uint32_t C, target, ranks_cap, Q, lag;
+    uint32_t C, target, ranks_cap, Q, lag, sample;
     uint64_t sp_cap;
 };
+
+constexpr uint32_t kDefaultSizeSample = 8;
 
 LdsSizing lds_sizing(const gerbil_params* p, uint64_t n_bytes) {
     LdsSizing z;
@@ -213,16 +216,33 @@ LdsSizing lds_sizing(const gerbil_params* p, uint64_t n_bytes) {
         z.Q = 1;
     }
     z.lag = z.Q / 2;
+    z.sample = p->size_sample ? p->size_sample : kDefaultSizeSample;
     return z;
 }
 
-// Keys a slot must hold: the largest rank (bin, or hash slice of a bin) with slack for hash variance.
+// Keys a slot must hold: the largest rank (bin, or hash slice of a bin) with
+// slack for hash variance, plus the margins of its sampled run capacities:
+// with S the sampling step and L its segment length, N keys in P runs, the
+// capacities add up to at most N + 4 sqrt(S L N) (error of the sampled
+// total) + 4 sqrt(S L) sqrt(P (N + P L)) (sum of the per-run margins, by
+// Cauchy-Schwarz) + 32 P.
 uint64_t lds_slot_keys(uint64_t max_kmers, const LdsSizing& z) {
     const uint64_t per_slice = (uint64_t)kLdsMaxSub * z.target;
     uint64_t V = (max_kmers + per_slice - 1) / per_slice;
-    if (V <= 1) return std::max<uint64_t>(max_kmers, 1);
-    uint64_t est = (uint64_t)((double)max_kmers / (double)V * 1.25) + 65536;
-    return std::min(est, max_kmers);
+    double N;
+    if (V <= 1) {
+        N = (double)std::max<uint64_t>(max_kmers, 1);
+    } else {
+        N = std::min((double)max_kmers / (double)V * 1.25 + 65536.0, (double)max_kmers);
+    }
+    if (z.sample <= 1) return (uint64_t)N;
+    const double S = z.sample;
+    double P = std::ceil(N / z.target);
+    if (P < 1) P = 1;
+    if (P > kLdsMaxSub) P = kLdsMaxSub;
+    const double L = sample_seg_len(z.sample);
+    const double bound = N + 4.0 * std::sqrt(S * L * N) + 4.0 * std::sqrt(S * L) * std::sqrt(P * (N + P * L)) + 33.0 * P;
+    return (uint64_t)std::ceil(bound);
 }
 
 struct LdsLayout {
@@ -362,6 +382,7 @@ int32_t count_lds(const gerbil_bins* bins, const gerbil_params* p, void* ws, uin
     l.Q = z.Q;
     l.lag = z.lag;
     l.target = z.target;
+    l.sample = z.sample;
     l.table_slots = z.C;
     l.theta = p->max_probes ? p->max_probes : kDefaultLdsTheta;
     l.stage_clocks = p->stage_clocks;

@@ -1,6 +1,7 @@
 // Internal launch interface between the C-ABI layer and the kernels.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
 
 namespace gerbil {
@@ -134,6 +135,18 @@ inline uint32_t tail_bytes_for(uint32_t k) {
     const uint32_t W = (k + 31) / 32, r = k - 32 * (W - 1);
     return r <= 4 ? 1u : r <= 8 ? 2u : r <= 16 ? 4u : 8u;
 }
+// Run sizing from a sample: every S-th segment of L = kSegMax / S k-mers is
+// counted. A sampled segment adds at most L keys to any run, so the estimate
+// S c of a run holding n keys has variance at most S L n, whatever the input
+// (clumps of one key included). A run gets S c plus four standard deviations
+// of that bound plus a floor; with S = 1 the count is exact.
+constexpr uint32_t kSegMax = 32;
+__host__ __device__ inline uint32_t sample_seg_len(uint32_t S) { return S >= kSegMax ? 1u : kSegMax / S; }
+__host__ __device__ inline uint64_t run_capacity(uint64_t c, uint32_t S) {
+    if (S <= 1) return c;
+    const double L = sample_seg_len(S), est = (double)S * (double)c;
+    return (uint64_t)est + (uint64_t)(4.0 * sqrt((double)S * L * (est + L))) + 32ull;
+}
 inline uint64_t slot_words_for(uint64_t slot_keys, uint32_t k) {
     const uint32_t W = (k + 31) / 32;
     return slot_keys * (W - 1) + (slot_keys * tail_bytes_for(k) + 7) / 8;
@@ -176,6 +189,7 @@ struct LdsArgs {
     uint32_t tail_bytes;
     uint32_t Q, lag;
     uint32_t target;          // keys per sub-table
+    uint32_t sample;          // sub-table runs sized from every sample-th super-mer (1 = all)
     uint32_t table_slots;     // LDS slots per sub-table
     uint32_t theta;           // probes per key before the emergency area
     uint64_t* stage_clocks;   // optional [8]: busy wall-clock ticks per stage, then items per stage

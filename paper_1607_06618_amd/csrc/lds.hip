@@ -242,7 +242,6 @@ __device__ __forceinline__ uint32_t load_chunk_seg(const CountArgs& a, const Lds
 // complement into the reverse-complement key. A segment adds at most 32 new
 // bases, all inside the two packed words read at its start, so rolling never
 // waits for memory.
-constexpr uint32_t kSegMax = 32;
 
 template <int W>
 struct Segment {
@@ -398,10 +397,12 @@ __device__ void stage_count(const CountArgs& a, const LdsArgs& l, const Lds& s, 
     static_assert(kChunkHeader + 4 * kLdsMaxSub <= kLdsBytes - kLdsReserved, "count stage exceeds the LDS budget");
     uint32_t* hist = (uint32_t*)c.rest;
     for (uint32_t j = tid; j < P; j += kLdsBlock) hist[j] = 0;
-    const uint32_t S = load_chunk_seg(a, l, b, chunk, kSegMax, c.sdesc, c.sgpre, c.wsum);
-    for (uint32_t sg = tid; sg < S; sg += kLdsBlock) {
+    // with sampling, segments are short and only every l.sample-th one is walked
+    const uint32_t smp = l.sample > 1 ? l.sample : 1u, L = smp > 1 ? sample_seg_len(smp) : kSegMax;
+    const uint32_t S = load_chunk_seg(a, l, b, chunk, L, c.sdesc, c.sgpre, c.wsum);
+    for (uint32_t sg = tid * smp; sg < S; sg += kLdsBlock * smp) {
         Segment<W> g;
-        seg_open<W>(a, c.sdesc, c.sgpre, sg, kSegMax, g);
+        seg_open<W>(a, c.sdesc, c.sgpre, sg, L, g);
         if (!g.ok) continue;
         for (uint32_t j = 0; j < g.len; j++) {
             if (j) seg_step<W>(a.k, g);
@@ -425,9 +426,15 @@ __device__ void stage_scan(const CountArgs& a, const LdsArgs& l, const Lds& s, u
     uint64_t* part = (uint64_t*)s.u;
     const uint32_t per = (P + kLdsBlock - 1) / kLdsBlock;
     uint64_t sum = 0;
+    // sampled counts -> run capacities (sp_cnt then holds the capacity)
     for (uint32_t e = 0; e < per; e++) {
         uint32_t j = tid * per + e;
-        if (j < P) sum += ld_dev(&l.sp_cnt[sb + j]);
+        if (j < P) {
+            uint64_t cap = run_capacity(ld_dev(&l.sp_cnt[sb + j]), l.sample);
+            if (cap > 0xFFFFFFFFull) cap = 0xFFFFFFFFull;
+            st_dev(&l.sp_cnt[sb + j], (uint32_t)cap);
+            sum += cap;
+        }
     }
     part[tid] = sum;
     __syncthreads();
@@ -505,8 +512,9 @@ __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s
             const uint32_t n = cnt[j];
             if (n) {
                 const uint32_t gsub = add_dev(&l.sp_cur[sb + j], n);
+                const uint32_t cap = ld_dev(&l.sp_cnt[sb + j]);
                 dst[j] = (uint32_t)(ld_dev(&l.sp_off[sb + j]) + gsub);
-                cnt[j] = 0;
+                cnt[j] = gsub >= cap ? 0u : (cap - gsub < n ? cap - gsub : n);   // keys that fit the run
             }
         }
 #pragma unroll
@@ -523,16 +531,28 @@ __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s
                 uint32_t mid = (lo + hi) >> 1;
                 if (lp[mid] <= i) lo = mid; else hi = mid;
             }
-            const uint64_t gpos = (uint64_t)dst[lo] + (i - lp[lo]);
-            if (gpos < l.slot_keys) {
+            const uint32_t q = i - lp[lo];
+            if (q < cnt[lo]) {
+                const uint64_t gpos = (uint64_t)dst[lo] + q;
+                if (gpos < l.slot_keys) {
 #pragma unroll
-                for (int w = 0; w + 1 < W; w++) st_dev(&slot[(uint64_t)w * l.slot_keys + gpos], buf[(uint64_t)i * W + w]);
-                store_tail(tail, gpos, buf[(uint64_t)i * W + W - 1], l.tail_bytes);
+                    for (int w = 0; w + 1 < W; w++)
+                        st_dev(&slot[(uint64_t)w * l.slot_keys + gpos], buf[(uint64_t)i * W + w]);
+                    store_tail(tail, gpos, buf[(uint64_t)i * W + W - 1], l.tail_bytes);
+                } else {
+                    set_status(a.status, ST_POOL);
+                }
             } else {
-                set_status(a.status, ST_POOL);
+                // past the end of its run (the run was sized from a sample): emergency area
+                uint64_t key[W];
+#pragma unroll
+                for (int w = 0; w < W; w++) key[w] = buf[(uint64_t)i * W + w];
+                overflow_push<W>(a, key);
             }
         }
         __syncthreads();
+        for (uint32_t j = tid; j < P; j += kLdsBlock) cnt[j] = 0;
+        __syncthreads();   // counts cleared before the next round adds to them
     }
 }
 
@@ -613,18 +633,23 @@ __device__ void stage_table(const CountArgs& a, const LdsArgs& l, const Lds& s, 
     uint32_t* wsum = cnt + C + 1;
     uint64_t* s_base = (uint64_t*)(((uintptr_t)(wsum + 32) + 7) & ~(uintptr_t)7);
     const uint64_t sb = l.rank_spbase[r];
-    const uint64_t n = ld_dev(&l.sp_cnt[sb + j]);
+    const uint32_t n_put = ld_dev(&l.sp_cur[sb + j]), n_cap = ld_dev(&l.sp_cnt[sb + j]);
+    const uint64_t n = n_put < n_cap ? n_put : n_cap;   // keys written to the run
     const uint64_t off = ld_dev(&l.sp_off[sb + j]);
     // the slot holds its keys word-major (word w of run position i at
     // w * slot_keys + i), so each word of a batch is one coalesced load per wave
     const uint64_t* keys = l.keys + (uint64_t)(r % l.Q) * l.slot_words + off;
     const uint8_t* tail = (const uint8_t*)(l.keys + (uint64_t)(r % l.Q) * l.slot_words + (uint64_t)(W - 1) * l.slot_keys);
+    const uint64_t lim = (off + n <= l.slot_keys) ? n : 0;   // a run past the slot was never written
+    // A run sized from a sample can overflow while keys are scattered; the
+    // keys past its end are then already in the emergency area, so every key
+    // of this sub-table goes there too and each key is counted in one place.
+    const bool spill = n_put > n_cap;
     for (uint32_t i = tid; i < C; i += kLdsBlock) {
         w0[i] = GERBIL_EMPTY;
         cnt[i] = 0;
     }
     __syncthreads();
-    const uint64_t lim = (off + n <= l.slot_keys) ? n : 0;   // a run past the slot was never written
     for (uint64_t base = 0; base < lim; base += (uint64_t)kLdsBlock * K) {
         // every lane loads K keys (lanes past the run re-read its last key and
         // drop it), so all loads of the batch are in flight together
@@ -644,8 +669,8 @@ __device__ void stage_table(const CountArgs& a, const LdsArgs& l, const Lds& s, 
         for (int e = 0; e < K; e++) {
             const uint64_t i = base + (uint64_t)e * kLdsBlock + tid;
             if (i < lim) {
-                const uint64_t h = key_hash<W>(key[e], a.seed);
-                if (!lds_insert<W>(w0, rest, cnt, C, l.theta, key[e], h, a.status)) overflow_push<W>(a, key[e]);
+                if (spill || !lds_insert<W>(w0, rest, cnt, C, l.theta, key[e], key_hash<W>(key[e], a.seed), a.status))
+                    overflow_push<W>(a, key[e]);
             }
         }
     }

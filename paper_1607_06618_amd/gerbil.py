@@ -47,7 +47,8 @@ class gerbil_params(ctypes.Structure):
     _fields_ = [("k", u32), ("m", u32), ("n_bins", u32), ("threshold", u32), ("canonical", u32),
                 ("order", u32), ("bin_map", vp), ("mode", u32), ("table", u32), ("load_factor", f32),
                 ("max_probes", u32), ("block", u32), ("pool", u32), ("overflow_cap", u64),
-                ("superm_cap", u64), ("table_budget", u64), ("timing_events", vp), ("stage_clocks", vp)]
+                ("superm_cap", u64), ("table_budget", u64), ("timing_events", vp), ("stage_clocks", vp),
+                ("size_sample", u32), ("reserved0", u32)]
 
 
 class gerbil_encoded(ctypes.Structure):
@@ -265,12 +266,13 @@ def words(k: int) -> int:
 def make_params(k: int, m: int, n_bins: int, threshold: int, mode: int = GERBIL_PLAIN, order: int = 0,
                 bin_map_ptr: int = 0, load_factor: float = 0.0, max_probes: int = 0, block: int = 0,
                 table: int = GERBIL_TABLE_AUTO, pool: int = 0, overflow_cap: int = 0, superm_cap: int = 0,
-                table_budget: int = 0, timing_events: int = 0, stage_clocks: int = 0) -> gerbil_params:
+                table_budget: int = 0, timing_events: int = 0, stage_clocks: int = 0,
+                size_sample: int = 0) -> gerbil_params:
     return gerbil_params(k=k, m=m, n_bins=n_bins, threshold=threshold, canonical=1, order=order,
                          bin_map=bin_map_ptr or None, mode=mode, table=table, load_factor=load_factor,
                          max_probes=max_probes, block=block, pool=pool, overflow_cap=overflow_cap,
                          superm_cap=superm_cap, table_budget=table_budget, timing_events=timing_events or None,
-                         stage_clocks=stage_clocks or None)
+                         stage_clocks=stage_clocks or None, size_sample=size_sample)
 
 
 @dataclass

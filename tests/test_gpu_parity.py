@@ -297,3 +297,27 @@ def test_lds_key_slots(pool):
     a, o = w.generate()
     run_and_compare(a, o, w.k, w.m, 64, w.threshold, hist_len=256, table=g.GERBIL_TABLE_LDS,
                     mode=g.GERBIL_BATCHED, pool=pool)
+
+
+def test_sampled_run_sizes_spill_to_the_emergency_area_exactly():
+    """LDS key runs are sized from every S-th super-mer. Homopolymer stretches
+    put long clumps of one canonical key into single super-mers, so sampled
+    sizes miss by more than their margin and keys spill past their run end;
+    those keys take the emergency area and every count stays exact."""
+    rng = np.random.default_rng(77)
+    reads = []
+    for _ in range(600):
+        pre = "".join(np.array(list("ACGT"))[rng.integers(0, 4, int(rng.integers(20, 60)))].tolist())
+        suf = "".join(np.array(list("ACGT"))[rng.integers(0, 4, int(rng.integers(20, 60)))].tolist())
+        reads.append(pre + str(rng.choice(list("AC"))) * int(rng.integers(100, 400)) + suf)
+    a, o = reads_to_csr(reads)
+    spilled = []
+    for S in (1, 2, 3, 7, 64, 1000):
+        for mode in (g.GERBIL_BATCHED, g.GERBIL_PLAIN):
+            res, _ = run_and_compare(a, o, 32, 7, 4, 1, hist_len=128, table=g.GERBIL_TABLE_LDS, mode=mode,
+                                     size_sample=S)
+            if S == 1:
+                assert res.report.n_overflow == 0, "exact run sizes never spill"
+            else:
+                spilled.append(res.report.n_overflow)
+    assert max(spilled) > 0, "no sampled run overflowed: the spill path was not exercised"
