@@ -208,11 +208,13 @@ hipError_t launch_lds_plan(const LdsArgs& l, hipStream_t s) {
 // ---------------------------------------------------------- LDS layout
 struct Lds {
     uint32_t* hist;     // [kLdsHist] count-of-counts, flushed at the end of the kernel
+    uint32_t* flag;     // one word for block-wide votes (last word of the reserved region)
     uint8_t* u;         // union region, carved per stage
 };
 __device__ __forceinline__ Lds lds_carve(uint8_t* base) {
     Lds x;
     x.hist = (uint32_t*)base;
+    x.flag = (uint32_t*)(base + kLdsReserved - 4);
     x.u = base + kLdsReserved;
     return x;
 }
@@ -253,9 +255,93 @@ struct Segment {
     bool ok;
 };
 
+// The packed words a segment needs, fetched without being used: the bases of
+// its first k-mer and the bases it rolls in lie in the W + 2 words from the
+// one holding its first base. Kept apart from seg_build so that the fetch
+// of the next segment can be issued while the current one is still in use.
+template <int W>
+struct SegRaw {
+    uint64_t w[W + 2];
+    int64_t p;      // position of the first k-mer
+    uint32_t len;   // k-mers in the segment
+    bool ok;
+};
+
+template <int W>
+__device__ __forceinline__ void seg_fetch(const CountArgs& a, const uint64_t* sdesc, const uint32_t* sgpre, uint32_t sg,
+                                          uint32_t L, SegRaw<W>& r) {
+    uint32_t lo = 0, hi = kLdsBlock;   // last descriptor whose first segment is <= sg
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (sgpre[mid] <= sg) lo = mid; else hi = mid;
+    }
+    const uint64_t d = sdesc[lo];
+    const int64_t start = (int64_t)(d >> 24);
+    const uint32_t n = (uint32_t)(d & 0xFFFFFFu);
+    const uint32_t off = (sg - sgpre[lo]) * L;
+    r.p = start + off;
+    r.len = n - off < L ? n - off : L;
+    r.ok = start >= 0 && (uint64_t)(r.p + r.len - 1) + a.k <= a.n_bytes;
+    if (!r.ok) {
+        set_status(a.status, ST_SPIN);   // a corrupt descriptor must not read out of range
+        return;
+    }
+    // the packed stream has two zero words past word (n_bytes-1)/32: indexes are clamped to the last
+    const int64_t q0 = r.p >> 5, last = (int64_t)((a.n_bytes + 31) >> 5) + 1;
+#pragma unroll
+    for (int j = 0; j < W + 2; j++) r.w[j] = a.packed[q0 + j < last ? q0 + j : last];
+}
+
+// Forward key, reverse-complement key and rolling words of a fetched segment,
+// from registers only. Word i < W-1 of the reverse complement is the
+// reverse complement of the 32 forward bases ending 32i bases before the end
+// (the last 32 - r bases of forward word W-2-i followed by the first r of
+// word W-1-i, r = k - 32(W-1)); its last word is that of the first r bases.
+template <int W>
+__device__ __forceinline__ void seg_build(const SegRaw<W>& r, uint32_t k, Segment<W>& g) {
+    g.p = r.p;
+    g.len = r.len;
+    g.ok = r.ok;
+    const uint32_t o = (uint32_t)(r.p & 31);
+    const uint32_t rb = k - 32u * (W - 1), sh = 2u * (32u - rb);
+    const uint64_t tmask = rb == 32 ? ~0ull : ((1ull << (2 * rb)) - 1ull);
+#pragma unroll
+    for (int i = 0; i < W; i++) {
+        const uint64_t x = o ? ((r.w[i] << (2 * o)) | (r.w[i + 1] >> (64 - 2 * o))) : r.w[i];
+        g.fw[i] = (i == W - 1 && sh) ? (x >> sh) : x;
+    }
+    if (W == 1) {
+        g.rc[0] = revcomp32(sh ? (g.fw[0] << sh) : g.fw[0]) & tmask;
+    } else {
+#pragma unroll
+        for (int i = 0; i + 1 < W; i++) {
+            uint64_t x;
+            if (rb == 32) x = g.fw[W - 1 - i];
+            else if (i == 0) x = (g.fw[W - 2] << (2 * rb)) | g.fw[W - 1];
+            else x = (g.fw[W - 2 - i] << (2 * rb)) | (g.fw[W - 1 - i] >> (64 - 2 * rb));
+            g.rc[i] = revcomp32(x);
+        }
+        g.rc[W - 1] = revcomp32(g.fw[0]) & tmask;
+    }
+    g.q = (r.p + (int64_t)k) >> 5;   // word of the next base to roll in: word W-1 or W of the fetch
+    const bool hiw = ((o + k) >> 5) == (uint32_t)W;
+    g.cur = hiw ? r.w[W] : r.w[W - 1];
+    g.nxt = hiw ? r.w[W + 1] : r.w[W];
+}
+
+// Open a segment at once. Short keys go through seg_fetch/seg_build (W + 2
+// loads); longer keys read each 32-base window directly, which keeps fewer
+// words live at a time.
 template <int W>
 __device__ __forceinline__ void seg_open(const CountArgs& a, const uint64_t* sdesc, const uint32_t* sgpre, uint32_t sg,
                                          uint32_t L, Segment<W>& g) {
+    if (W <= 3) {
+        SegRaw<W> r;
+        seg_fetch<W>(a, sdesc, sgpre, sg, L, r);
+        if (r.ok) seg_build<W>(r, a.k, g);
+        else g.ok = false;
+        return;
+    }
     uint32_t lo = 0, hi = kLdsBlock;   // last descriptor whose first segment is <= sg
     while (hi - lo > 1) {
         uint32_t mid = (lo + hi) >> 1;
@@ -347,6 +433,16 @@ __device__ __forceinline__ void load_tails(const uint8_t* tail, uint64_t off, co
     }
 }
 
+// True on every thread if v is true on any thread (an LDS word, not static
+// shared memory: the kernels already take all 160 KB of dynamic LDS).
+__device__ __forceinline__ bool block_any(bool v, uint32_t* flag) {
+    if (threadIdx.x == 0) *flag = 0u;
+    __syncthreads();
+    if (v) *flag = 1u;
+    __syncthreads();
+    return *flag != 0u;
+}
+
 // Exclusive prefix of cnt[0..n) into pre[0..n) by the whole block; returns the total.
 __device__ __forceinline__ uint32_t block_scan_array(const uint32_t* cnt, uint32_t* pre, uint32_t n, uint32_t* wsum) {
     const uint32_t per = (n + kLdsBlock - 1) / kLdsBlock;
@@ -367,7 +463,7 @@ __device__ __forceinline__ uint32_t block_scan_array(const uint32_t* cnt, uint32
 // Round size of the scatter stage: R keys per thread (one segment of at most
 // R k-mers), staged in 96 KB of LDS at most.
 template <int W>
-struct ScatterRound { static constexpr int R = W == 1 ? 8 : W == 2 ? 6 : W == 3 ? 4 : W == 4 ? 3 : W == 5 ? 2 : 1; };
+struct ScatterRound { static constexpr int R = W == 1 ? 8 : W == 2 ? 5 : W == 3 ? 4 : W == 4 ? 3 : W == 5 ? 2 : 1; };
 
 // LDS of the chunk stages: descriptors, segment prefixes and scan scratch.
 constexpr uint32_t kChunkHeader = 8 * kLdsBlock + 4 * (kLdsBlock + 4) + 4 * 32;
@@ -481,6 +577,14 @@ __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s
     for (uint32_t j = tid; j < P; j += kLdsBlock) cnt[j] = 0;
     const uint32_t S = load_chunk_seg(a, l, b, chunk, R, c.sdesc, c.sgpre, c.wsum);
     const uint32_t rounds = (S + kLdsBlock - 1) / kLdsBlock;
+    // the segment of the next round is opened (its packed words requested)
+    // while the current round is written out
+    // For short keys the next round's words are fetched while this round is
+    // written out; longer keys (more registers per key) open at round start.
+    constexpr bool kAhead = W <= 3;
+    SegRaw<W> raw;
+    raw.ok = false;
+    if (kAhead && tid < S) seg_fetch<W>(a, c.sdesc, c.sgpre, tid, R, raw);
     for (uint32_t round = 0; round < rounds; round++) {
         uint64_t key[R][W];
         uint32_t sp[R], rk[R];
@@ -489,7 +593,12 @@ __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s
         const uint32_t sg = round * kLdsBlock + tid;
         if (sg < S) {
             Segment<W> g;
-            seg_open<W>(a, c.sdesc, c.sgpre, sg, R, g);
+            g.ok = false;
+            if (kAhead) {
+                if (raw.ok) seg_build<W>(raw, a.k, g);
+            } else {
+                seg_open<W>(a, c.sdesc, c.sgpre, sg, R, g);
+            }
             if (g.ok) {
 #pragma unroll
                 for (int e = 0; e < R; e++) {
@@ -524,7 +633,14 @@ __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s
 #pragma unroll
             for (int w = 0; w < W; w++) buf[(uint64_t)pos * W + w] = key[e][w];
         }
+        if (kAhead) {
+            raw.ok = false;
+            if (sg + kLdsBlock < S) seg_fetch<W>(a, c.sdesc, c.sgpre, sg + kLdsBlock, R, raw);
+        }
         __syncthreads();
+        // stores only: nothing in this loop waits for memory (a returning
+        // atomic here would make every iteration wait for all earlier stores)
+        uint32_t spilled = 0;
         for (uint32_t i = tid; i < T; i += kLdsBlock) {
             uint32_t lo = 0, hi = P;   // last sub-table whose run starts at or before i
             while (hi - lo > 1) {
@@ -543,7 +659,18 @@ __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s
                     set_status(a.status, ST_POOL);
                 }
             } else {
-                // past the end of its run (the run was sized from a sample): emergency area
+                spilled = 1;
+            }
+        }
+        // keys past the end of their run (runs are sized from a sample): emergency area
+        if (block_any(spilled != 0, s.flag)) {
+            for (uint32_t i = tid; i < T; i += kLdsBlock) {
+                uint32_t lo = 0, hi = P;
+                while (hi - lo > 1) {
+                    uint32_t mid = (lo + hi) >> 1;
+                    if (lp[mid] <= i) lo = mid; else hi = mid;
+                }
+                if (i - lp[lo] < cnt[lo]) continue;
                 uint64_t key[W];
 #pragma unroll
                 for (int w = 0; w < W; w++) key[w] = buf[(uint64_t)i * W + w];
@@ -665,13 +792,19 @@ __device__ void stage_table(const CountArgs& a, const LdsArgs& l, const Lds& s, 
 #pragma unroll
             for (int w = 0; w + 1 < W; w++) key[e][w] = ld_dev(&keys[(uint64_t)w * l.slot_keys + ix[e]]);
         load_tails<K, W>(tail, off, ix, l.tail_bytes, key);
+        uint32_t failed = 0;   // bit e: key e goes to the emergency area (pushed after the batch)
 #pragma unroll
         for (int e = 0; e < K; e++) {
             const uint64_t i = base + (uint64_t)e * kLdsBlock + tid;
             if (i < lim) {
                 if (spill || !lds_insert<W>(w0, rest, cnt, C, l.theta, key[e], key_hash<W>(key[e], a.seed), a.status))
-                    overflow_push<W>(a, key[e]);
+                    failed |= 1u << e;
             }
+        }
+        if (failed) {
+#pragma unroll
+            for (int e = 0; e < K; e++)
+                if (failed & (1u << e)) overflow_push<W>(a, key[e]);
         }
     }
     __syncthreads();
@@ -765,7 +898,7 @@ __global__ void __launch_bounds__(kLdsBlock) k_lds_persistent(CountArgs a, LdsAr
     uint64_t* s_item = (uint64_t*)(lds_raw + kLdsHist * 4);
     uint64_t* s_first = s_item + 1;
     uint32_t* s_seg = (uint32_t*)(s_item + 2);
-    static_assert(kLdsHist * 4 + 24 <= kLdsReserved, "queue scalars exceed the reserved LDS");
+    static_assert(kLdsHist * 4 + 24 <= kLdsReserved - 4, "queue scalars exceed the reserved LDS");
     const uint32_t tid = threadIdx.x;
     hist_begin(s);
     uint32_t wmax = 0;
