@@ -274,6 +274,83 @@ int oracle_count_keys(const uint8_t* ascii, const uint64_t* offsets, uint64_t n_
     return ORACLE_OK;
 }
 
+/* The same counts over reads [r0, r1) only, for queries against very large
+ * read sets (callers split the reads between threads and add the results).
+ * A window is canonicalised only when the first f = min(16, k) bases of its
+ * forward strand or of its reverse complement begin some query key: the
+ * canonical form is one of the two strands, so no window that matches a
+ * query is skipped. Windows are tested for undetermined bases with the end
+ * of the run of valid bases they start in (Sec. 2.4.1). */
+static int cmp_u32(const void* a, const void* b) {
+    uint32_t x = *(const uint32_t*)a, y = *(const uint32_t*)b;
+    return x < y ? -1 : x > y;
+}
+
+static int has_u32(const uint32_t* v, uint64_t n, uint32_t x) {
+    uint64_t lo = 0, hi = n;
+    while (lo < hi) {
+        uint64_t mid = (lo + hi) / 2;
+        if (v[mid] == x) return 1;
+        if (v[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return 0;
+}
+
+int oracle_count_keys_range(const uint8_t* ascii, const uint64_t* offsets, uint64_t r0, uint64_t r1, uint32_t k,
+                            const uint64_t* query /* [n_query * W], sorted ascending */, uint64_t n_query,
+                            uint64_t* counts /* [n_query], added to */) {
+    if (k < 1 || k > 1024) return ORACLE_EINVAL;
+    uint32_t W = words_for(k);
+    uint32_t f = k < 16 ? k : 16;
+    uint32_t r_last = k - 32 * (W - 1);
+    /* prefix code of every query key: its first f bases, 2 bits each */
+    uint32_t* pre = (uint32_t*)malloc(4 * (n_query ? n_query : 1));
+    for (uint64_t q = 0; q < n_query; q++) {
+        const uint64_t* key = query + q * W;
+        uint32_t c = 0;
+        for (uint32_t j = 0; j < f; j++) {
+            uint32_t wi = j / 32, bi = j % 32;
+            uint32_t bases_in_word = (wi == W - 1) ? r_last : 32;
+            c = (c << 2) | (uint32_t)((key[wi] >> (2 * (bases_in_word - 1 - bi))) & 3);
+        }
+        pre[q] = c;
+    }
+    qsort(pre, n_query, 4, cmp_u32);
+    char* s = (char*)malloc(k);
+    char* t = (char*)malloc(k);
+    uint64_t* key = (uint64_t*)malloc(8 * W);
+    for (uint64_t r = r0; r < r1; r++) {
+        const uint8_t* R = ascii + offsets[r];
+        uint64_t L = offsets[r + 1] - offsets[r];
+        uint64_t run_end = 0;   /* first invalid position at or after i */
+        for (uint64_t i = 0; i + k <= L; i++) {
+            if (run_end <= i) {
+                run_end = i;
+                while (run_end < L && base_ok(R[run_end])) run_end++;
+            }
+            if (run_end < i + k) continue;   /* the window holds an undetermined base */
+            uint32_t cf = 0, cr = 0;
+            for (uint32_t j = 0; j < f; j++) {
+                cf = (cf << 2) | (uint32_t)code2(upper(R[i + j]));
+                cr = (cr << 2) | (uint32_t)code2(complement(upper(R[i + k - 1 - j])));
+            }
+            if (!has_u32(pre, n_query, cf) && !has_u32(pre, n_query, cr)) continue;
+            for (uint32_t j = 0; j < k; j++) s[j] = upper(R[i + j]);
+            reverse_complement(s, k, t);
+            pack(memcmp(t, s, k) < 0 ? t : s, k, key);
+            uint64_t lo = 0, hi = n_query;
+            while (lo < hi) {
+                uint64_t mid = (lo + hi) / 2;
+                int c = cmp_keys(query + mid * W, key, &W);
+                if (c == 0) { counts[mid]++; break; }
+                if (c < 0) lo = mid + 1; else hi = mid;
+            }
+        }
+    }
+    free(s); free(t); free(key); free(pre);
+    return ORACLE_OK;
+}
+
 /* ------------------------------------------------------------- encoding -- */
 
 /*

@@ -29,7 +29,6 @@ constexpr uint32_t kNone = 0xFFFFFFFFu;
 
 __device__ __forceinline__ uint32_t slice_of(uint64_t h, uint32_t V) { return fastrange32((uint32_t)(h >> 32), V); }
 __device__ __forceinline__ uint32_t sub_of(uint64_t h, uint32_t P) { return fastrange32((uint32_t)h, P); }
-__device__ __forceinline__ uint64_t lds_hash(uint64_t h) { return fmix64(h ^ 0x5851F42D4C957F2Dull); }
 
 // ----------------------------------------------------------------- plan
 // One workgroup. Ranks follow the bins in LPT order (largest first); a bin
@@ -690,11 +689,13 @@ template <int W>
 __device__ __forceinline__ bool lds_insert(uint64_t* w0, uint64_t* rest, uint32_t* cnt, uint32_t C, uint32_t theta,
                                            const uint64_t (&key)[W], uint64_t h, uint32_t* status) {
     if (W > 1 && key[0] == GERBIL_EMPTY) return false;
-    // C is prime and 1 <= step < C: double hashing visits theta distinct slots
-    const uint64_t hh = lds_hash(h);
-    const uint32_t step = 1u + fastrange32((uint32_t)(hh >> 32), C - 1);
+    // C is prime and 1 <= step < C: double hashing visits theta distinct slots.
+    // The sub-table is chosen by the top bits of h's low half and the slice by
+    // the top bits of its high half, so the slot and the step take bits 0-19
+    // and 32-51, which neither choice depends on.
+    const uint32_t step = 1u + fastrange32((uint32_t)((h >> 32) << 12), C - 1);
     uint32_t t = 0, spins = 0;
-    uint32_t sl = fastrange32((uint32_t)hh, C);
+    uint32_t sl = fastrange32((uint32_t)(h << 12), C);
     for (;;) {
         uint64_t cur = __hip_atomic_load(w0 + sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (cur == GERBIL_EMPTY) {
@@ -728,8 +729,8 @@ __device__ __forceinline__ bool lds_insert(uint64_t* w0, uint64_t* rest, uint32_
 #pragma unroll
             for (int i = 1; i < W; i++) eq &= rest[(uint32_t)(i - 1) * C + sl] == key[i];
             if (eq) {
-                uint32_t old = __hip_atomic_fetch_add(cnt + sl, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                if (old >= 0xFFFFFFFEu) set_status(status, ST_COUNT_SAT);
+                // a run holds fewer than 2^32 keys, so a count cannot wrap
+                __hip_atomic_fetch_add(cnt + sl, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 return true;
             }
         }

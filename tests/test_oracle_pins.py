@@ -330,3 +330,28 @@ def test_shards_partition_the_result():
         assert p.n_valid == full.n_valid
     assert merged == oracle_dict(full)
     assert sum(p.n_valid_shard for p in parts) == full.n_valid
+
+
+@pytest.mark.parametrize("k", [3, 9, 15, 16, 17, 31, 32, 33, 65, 200])
+def test_parallel_prefiltered_count_keys_matches_plain_count_keys(k):
+    """The prefiltered, read-split key count is the plain one: queries hold
+    present keys, absent keys and absent keys sharing a present key's prefix."""
+    rng = random.Random(100 + k)
+    reads = random_reads(rng, 120, k + 120, n_rate=0.01)
+    reads = [r.lower() if i % 7 == 0 else r for i, r in enumerate(reads)]
+    a, o = reads_to_csr(reads)
+    res = oracle.count(a, o, k=k, threshold=1)
+    present = res.keys[:: max(1, res.keys.shape[0] // 40)]
+    W = present.shape[1]
+    nrng = np.random.default_rng(k)
+    absent = nrng.integers(0, 2**63, size=(20, W), dtype=np.int64).view(np.uint64)
+    r_last = k - 32 * (W - 1)
+    if r_last < 32:
+        absent[:, -1] &= np.uint64((1 << (2 * r_last)) - 1)
+    near = present[:10].copy()
+    near[:, -1] ^= np.uint64(1)   # same prefix, last base changed
+    query = np.unique(np.concatenate([present, absent, near]), axis=0)
+    want = oracle.count_keys(a, o, k, query)
+    got = oracle.count_keys_parallel(a, o, k, query, threads=3)
+    assert np.array_equal(got, want)
+    assert (want > 0).sum() >= present.shape[0] // 2
