@@ -398,13 +398,13 @@ __device__ __forceinline__ void seg_step(uint32_t k, Segment<W>& g) {
     roll_base<W>(g.fw, g.rc, b, k);
 }
 
-// The last word of key i of a slot, stored in `tb` bytes (device-coherent).
+// The last word of key i of a slot, stored in `tb` bytes (plain store).
 __device__ __forceinline__ void store_tail(uint8_t* tail, uint64_t i, uint64_t v, uint32_t tb) {
     switch (tb) {
-        case 1: st_dev(tail + i, (uint8_t)v); break;
-        case 2: st_dev((uint16_t*)tail + i, (uint16_t)v); break;
-        case 4: st_dev((uint32_t*)tail + i, (uint32_t)v); break;
-        default: st_dev((uint64_t*)tail + i, v); break;
+        case 1: tail[i] = (uint8_t)v; break;
+        case 2: ((uint16_t*)tail)[i] = (uint16_t)v; break;
+        case 4: ((uint32_t*)tail)[i] = (uint32_t)v; break;
+        default: ((uint64_t*)tail)[i] = v; break;
     }
 }
 
@@ -650,9 +650,11 @@ __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s
             if (q < cnt[lo]) {
                 const uint64_t gpos = (uint64_t)dst[lo] + q;
                 if (gpos < l.slot_keys) {
+                    // plain stores: merged in L2 and written back once, by the
+                    // release fence that ends the item (see the persistent loop)
 #pragma unroll
                     for (int w = 0; w + 1 < W; w++)
-                        st_dev(&slot[(uint64_t)w * l.slot_keys + gpos], buf[(uint64_t)i * W + w]);
+                        slot[(uint64_t)w * l.slot_keys + gpos] = buf[(uint64_t)i * W + w];
                     store_tail(tail, gpos, buf[(uint64_t)i * W + W - 1], l.tail_bytes);
                 } else {
                     set_status(a.status, ST_POOL);
@@ -939,13 +941,24 @@ __global__ void __launch_bounds__(kLdsBlock) k_lds_persistent(CountArgs a, LdsAr
         __syncthreads();
         const uint64_t t0 = l.stage_clocks ? wall_clock64() : 0;
         run_stage<W>(a, l, s, st, r, local, wmax);
-        // Stages 0-2 publish data that later stages read, so their stores are
-        // drained first. The table stage only releases its key slot: its key
-        // loads have completed (their values were inserted), and its output
-        // stores are read by no other stage, so it signals without a drain.
+        // Stages 0 and 1 publish with device-coherent stores and atomics, so a
+        // drain before the signal suffices. The scatter writes its keys with
+        // plain stores (merged in this XCD's L2): once every wave has drained
+        // them into L2, one agent-scope release fence writes L2 back to memory
+        // before the signal, and readers load the keys device-coherently. The
+        // table stage only releases its key slot: its key loads have completed
+        // (their values were inserted), and its output stores are read by no
+        // other stage, so it signals without a drain.
         if (st == 3) {
             __syncthreads();
             if (tid == 0) __hip_atomic_fetch_add(l.done + 4 * r + st, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (st == 2) {
+            drain_memory();
+            __syncthreads();
+            if (tid == 0) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __hip_atomic_fetch_add(l.done + 4 * r + st, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         } else {
             signal_done(l.done + 4 * r + st);
         }
