@@ -92,8 +92,11 @@ typedef struct {
                                 bin = rank mod n_bins                                             */
     uint32_t mode;           /* GERBIL_PLAIN or GERBIL_BATCHED                                   */
     uint32_t table;          /* GERBIL_TABLE_*                                                   */
-    float load_factor;       /* k-mers per table slot when tables are sized (k-mers bound the
-                                distinct keys), (0, 0.95]; 0 = default (0.5 HBM, 0.8 LDS)       */
+    float load_factor;       /* k-mers per table slot when tables are sized: HBM tables (0, 0.95]
+                                (k-mers bound the distinct keys), default 0.5; LDS sub-tables
+                                (0, 4], default 0.8 (occurrences repeat, so more than one per
+                                slot can fit; distinct keys beyond the slots take the emergency
+                                area)                                                             */
     uint32_t max_probes;     /* theta of Alg. 1: trials before the emergency path; 0 = default
                                 (8 buckets of 8 slots in HBM tables, 64 slots in LDS tables)     */
     uint32_t block;          /* threads per workgroup for counting, 64..1024; 0 = default        */
@@ -320,7 +323,7 @@ int32_t gerbil_autotune_workspace(const gerbil_bins* bins, const gerbil_params* 
                                   hipStream_t stream);
 
 /* Time gerbil_count on `bins` for each candidate of the grid (LDS tables:
- * load_factor 0.6/0.7/0.8/0.9 x pool 4/8/16; HBM tables: load_factor 0.4/0.6
+ * load_factor 0.6/0.8/1.0/1.2 x pool 4/8/16; HBM tables: load_factor 0.4/0.6
  * x pool 8/32; p->table = LDS or HBM restricts the grid to that placement;
  * PLAIN mode has no pool) and write into *best a copy of *p with table,
  * load_factor and pool of the fastest candidate that finished without a

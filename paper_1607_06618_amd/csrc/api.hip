@@ -121,7 +121,12 @@ int32_t check_params(const gerbil_params* p) {
     if (p->n_bins < 1 || p->n_bins > kMaxBins) return GERBIL_EINVAL;
     if (p->threshold < 1) return GERBIL_EINVAL;
     if (p->order > 1 || p->mode > 1 || p->table > 2) return GERBIL_EINVAL;
-    if (p->load_factor < 0.0f || p->load_factor > 0.95f) return GERBIL_EINVAL;
+    // HBM tables hold every distinct key of a bin: at most 0.95 per slot. LDS
+    // sub-tables are sized in k-mer occurrences, which repeat, so more than
+    // one per slot can still fit (distinct keys beyond the slots go to the
+    // emergency area, exactly).
+    const float max_load = p->table == GERBIL_TABLE_HBM ? 0.95f : 4.0f;
+    if (p->load_factor < 0.0f || p->load_factor > max_load) return GERBIL_EINVAL;
     if (p->block && (p->block < 64 || p->block > 1024 || (p->block & 63))) return GERBIL_EINVAL;
     if (p->k > 32 * GERBIL_MAX_W) return GERBIL_EUNSUPPORTED;
     if (!p->canonical) return GERBIL_EUNSUPPORTED;

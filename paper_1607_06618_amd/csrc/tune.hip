@@ -36,7 +36,7 @@ std::vector<Candidate> candidates(const gerbil_params* p) {
     std::vector<Candidate> c;
     const bool batched = p->mode == GERBIL_BATCHED;
     if (p->table != GERBIL_TABLE_HBM) {
-        const float fills[] = {0.6f, 0.7f, 0.8f, 0.9f};
+        const float fills[] = {0.6f, 0.8f, 1.0f, 1.2f};
         const uint32_t pools[] = {4, 8, 16};
         for (float f : fills) {
             if (batched)

@@ -50,9 +50,13 @@ def test_param_validation_before_launch():
     enc = g.gerbil_encoded(n_reads=1, n_bytes=100, k=32)
     good = g.make_params(32, 7, 64, 2)
     assert g.gerbil_bin_workspace(enc, good) > 0
+    # LDS sub-tables are sized in k-mer occurrences: more than one per slot is allowed
+    assert g.gerbil_bin_workspace(enc, g.make_params(32, 7, 64, 2, load_factor=1.2)) > 0
     for bad in (g.make_params(32, 32, 64, 2), g.make_params(32, 0, 64, 2), g.make_params(32, 16, 64, 2),
                 g.make_params(32, 7, 0, 2), g.make_params(32, 7, 5000, 2), g.make_params(32, 7, 64, 0),
-                g.make_params(32, 7, 64, 2, block=100), g.make_params(32, 7, 64, 2, load_factor=0.99)):
+                g.make_params(32, 7, 64, 2, block=100),
+                g.make_params(32, 7, 64, 2, load_factor=0.99, table=g.GERBIL_TABLE_HBM),
+                g.make_params(32, 7, 64, 2, load_factor=4.5)):
         with pytest.raises(g.GerbilError) as e:
             g.gerbil_bin_workspace(enc, bad)
         assert e.value.status == g.GERBIL_EINVAL
