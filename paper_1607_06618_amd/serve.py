@@ -80,7 +80,7 @@ def footprint(n_bytes: int, n_reads: int, k: int, m: int, n_bins: int, threshold
     superm = min(n_bytes, n_bytes * 4 // (w + 1) + n_bytes // 2048 + 4096)
     bins = superm * 20 + n_bins * 32
     keys = 8 * 2 * n_bytes * 8 * W // max(1, n_bins) + (1 << 24)      # key slots, bins up to 2x the mean
-    out = (n_bytes // (8 * threshold) + 1) * (8 * W + 4)               # first output guess
+    out = (n_bytes // (2 * threshold) + 1) * (8 * W + 4)               # first output guess
     return ascii_b + enc + bins + keys + out + (1 << 22)
 
 
@@ -119,8 +119,9 @@ class _Job:
             if st != g.GERBIL_OK:
                 raise g.GerbilError("gerbil_result", st, rep)
             self.n_valid = rep.n_valid
-            # first output guess: an eighth of the windows can reach the threshold
-            self.job.cap = max(1024, rep.n_valid // (8 * self.req.threshold) + 1)
+            # first output guess: at most n_valid / t keys reach the threshold; with
+            # coverage above ~7x the distinct keys that do are below n_valid / (2t)
+            self.job.cap = max(1024, rep.n_valid // (2 * self.req.threshold) + 1)
             self.job.prepare_count(n_valid=rep.n_valid)
             self.job.count()
             self.ev.record(self.stream)
