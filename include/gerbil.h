@@ -343,6 +343,29 @@ int32_t gerbil_autotune(const gerbil_bins* bins, const gerbil_params* p, void* w
 /* Forget every cached autotuner choice. */
 int32_t gerbil_autotune_reset(void);
 
+/* ------------------------------------------------------------------------
+ * Output records (App. C): the binary file format of the counted pairs.
+ * ------------------------------------------------------------------------ */
+
+/* Workspace bytes gerbil_records needs for n pairs. */
+int32_t gerbil_records_workspace(uint64_t n, uint64_t* bytes);
+
+/* Encode n pairs as the binary records of App. C, back to back in pair order:
+ * the counter (one byte if it is below 255, else the byte 0xFF and the count
+ * as a big-endian 32-bit word), then the k-mer with four bases per byte, the
+ * first base in the two top bits, and the last byte padded with zero bits.
+ *   keys       device uint64 [n * W] (the layout gerbil_count emits)
+ *   counts     device uint32 [n]
+ *   ws         device workspace of gerbil_records_workspace(n) bytes, 256-byte aligned
+ *   out        device byte buffer of out_cap bytes
+ *   out_bytes  device uint64: receives the size of the whole stream. Bytes
+ *              past out_cap are not written; a caller whose buffer was too
+ *              small calls again with out_cap >= *out_bytes.
+ * Asynchronous on `stream`. Errors: GERBIL_EINVAL (bad arguments or
+ * workspace), GERBIL_EDEVICE (launch). */
+int32_t gerbil_records(const uint64_t* keys, const uint32_t* counts, uint64_t n, uint32_t k, void* ws,
+                       uint64_t ws_bytes, uint8_t* out, uint64_t out_cap, uint64_t* out_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

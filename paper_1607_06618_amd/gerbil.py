@@ -131,10 +131,13 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gerbil_autotune.argtypes = [P(gerbil_bins), P(gerbil_params), vp, u64, vp, vp, u64, P(gerbil_params),
                                     P(gerbil_tune_result), vp]
     lib.gerbil_autotune_reset.argtypes = []
+    lib.gerbil_records_workspace.argtypes = [u64, P(u64)]
+    lib.gerbil_records.argtypes = [vp, vp, u64, u32, vp, u64, vp, u64, vp, vp]
     for name in ("gerbil_encode_workspace", "gerbil_encode", "gerbil_bin_workspace", "gerbil_bin",
                  "gerbil_count_workspace", "gerbil_count", "gerbil_histogram", "gerbil_result",
                  "gerbil_graph_capture", "gerbil_graph_launch", "gerbil_graph_info", "gerbil_graph_destroy",
-                 "gerbil_autotune_workspace", "gerbil_autotune", "gerbil_autotune_reset"):
+                 "gerbil_autotune_workspace", "gerbil_autotune", "gerbil_autotune_reset",
+                 "gerbil_records_workspace", "gerbil_records"):
         getattr(lib, name).restype = ctypes.c_int32
     _lib = lib
     return lib
@@ -250,6 +253,38 @@ def gerbil_autotune(bins: gerbil_bins, p: gerbil_params, ws_ptr: int, ws_bytes: 
 
 def gerbil_autotune_reset() -> int:
     return load().gerbil_autotune_reset()
+
+
+def gerbil_records_workspace(n: int) -> int:
+    out = u64(0)
+    st = load().gerbil_records_workspace(n, ctypes.byref(out))
+    if st:
+        raise GerbilError("gerbil_records_workspace", st)
+    return out.value
+
+
+def gerbil_records(keys_ptr: int, counts_ptr: int, n: int, k: int, ws_ptr: int, ws_bytes: int, out_ptr: int,
+                   out_cap: int, out_bytes_ptr: int, stream: int = 0) -> int:
+    return load().gerbil_records(keys_ptr or None, counts_ptr or None, n, k, ws_ptr or None, ws_bytes,
+                                 out_ptr or None, out_cap, out_bytes_ptr, stream)
+
+
+def records(keys_d, counts_d, n: int, k: int, stream=None):
+    """The App. C record stream of n device pairs, as a device uint8 tensor."""
+    import torch
+    dev = counts_d.device
+    s = _stream_handle(stream)
+    ws = torch.empty(max(256, gerbil_records_workspace(n)), dtype=torch.uint8, device=dev)
+    size_d = torch.zeros(1, dtype=torch.int64, device=dev)
+    kb = (k + 3) // 4
+    cap = n * (5 + kb)   # every record at its largest
+    out = torch.empty(max(1, cap), dtype=torch.uint8, device=dev)
+    check("gerbil_records", gerbil_records(keys_d.data_ptr(), counts_d.data_ptr(), n, k, ws.data_ptr(), ws.numel(),
+                                           out.data_ptr(), cap, size_d.data_ptr(), s))
+    if stream is not None:
+        stream.synchronize()
+    size = int(size_d.item())
+    return out[:size]
 
 
 def check(fn: str, status: int):

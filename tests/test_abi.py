@@ -119,3 +119,17 @@ def test_autotune_validation():
     st, _, _ = g.gerbil_autotune(g.gerbil_bins(), p, 0, 0, 0, 0, 0, 1)
     assert st == g.GERBIL_EINVAL
     assert g.gerbil_autotune_reset() == g.GERBIL_OK
+
+
+def test_records_validation():
+    """Argument errors of the record codec come back before any device call."""
+    assert g.gerbil_records_workspace(0) == 256
+    assert g.gerbil_records_workspace(8192 * 3 + 1) >= 256 + 4 * 4 + 8 * 4
+    fake, ws_need = 4096, g.gerbil_records_workspace(100)
+    size = ctypes.c_uint64(0)
+    ok_args = dict(keys_ptr=fake, counts_ptr=fake, n=100, k=31, ws_ptr=4096, ws_bytes=ws_need, out_ptr=fake,
+                   out_cap=1000, out_bytes_ptr=ctypes.addressof(size))
+    for bad in (dict(out_bytes_ptr=None), dict(k=0), dict(k=257), dict(keys_ptr=0), dict(counts_ptr=0),
+                dict(ws_ptr=0), dict(ws_bytes=ws_need - 1), dict(ws_ptr=4096 + 8), dict(out_ptr=0)):
+        args = dict(ok_args, **bad)
+        assert g.gerbil_records(**args) == g.GERBIL_EINVAL, bad
