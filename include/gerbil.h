@@ -86,7 +86,8 @@ typedef struct {
     uint32_t m;              /* minimizer length, 1 <= m <= 15, m < k (App. A `-m`)              */
     uint32_t n_bins;         /* number of bins, 1..4096 (App. A `-f`, default 512)               */
     uint32_t threshold;      /* output iff count >= threshold, >= 1 (App. A `-l`, default 3)     */
-    uint32_t canonical;      /* 1: count canonical k-mers (Sec. 2.4.2). 0 (`-d`) unsupported     */
+    uint32_t canonical;      /* 1: count canonical k-mers (Sec. 2.4.2); 0: count each strand's  */
+                             /* k-mers as read (`-d`, App. A). Other values: GERBIL_EINVAL.    */
     uint32_t order;          /* GERBIL_ORDER_*                                                   */
     const uint32_t* bin_map; /* device [4^m] canonical m-mer code -> bin, or NULL for
                                 bin = rank mod n_bins                                             */

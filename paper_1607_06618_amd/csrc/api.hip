@@ -129,7 +129,7 @@ int32_t check_params(const gerbil_params* p) {
     if (p->load_factor < 0.0f || p->load_factor > max_load) return GERBIL_EINVAL;
     if (p->block && (p->block < 64 || p->block > 1024 || (p->block & 63))) return GERBIL_EINVAL;
     if (p->k > 32 * GERBIL_MAX_W) return GERBIL_EUNSUPPORTED;
-    if (!p->canonical) return GERBIL_EUNSUPPORTED;
+    if (p->canonical > 1) return GERBIL_EINVAL;
     return GERBIL_OK;
 }
 
@@ -330,6 +330,7 @@ CountArgs count_args(const gerbil_params* p, const gerbil_bins* bins, const gerb
     a.W = words_for(p->k);
     a.threshold = p->threshold;
     a.theta = p->max_probes ? p->max_probes : kDefaultTheta;
+    a.canonical = p->canonical;
     a.seed = kHashSeed;
     a.ovf_keys = L.ovf_keys;
     a.ovf_cap = state->overflow_cap;
@@ -645,6 +646,7 @@ int32_t gerbil_count(const gerbil_bins* bins, const gerbil_params* p, void* ws, 
     a.W = W;
     a.threshold = p->threshold;
     a.theta = p->max_probes ? p->max_probes : kDefaultTheta;
+    a.canonical = p->canonical;
     a.seed = kHashSeed;
     a.ovf_keys = L.ovf_keys;
     a.ovf_cap = ovf_cap;

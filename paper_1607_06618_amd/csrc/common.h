@@ -64,10 +64,12 @@ __device__ __forceinline__ void extract_kmer(const uint64_t* __restrict__ P, int
     rc[W - 1] = sh ? (rtail >> sh) : rtail;
 }
 
-// canonical = lexicographically smaller of fw and rc (compare from word 0).
+// canonical = lexicographically smaller of fw and rc (compare from word 0);
+// with canon false (the `-d` mode of App. A) the key is fw itself.
 template <int W>
-__device__ __forceinline__ void canonical_of(const uint64_t (&fw)[W], const uint64_t (&rc)[W], uint64_t (&key)[W]) {
-    bool take_rc = false, decided = false;
+__device__ __forceinline__ void canonical_of(const uint64_t (&fw)[W], const uint64_t (&rc)[W], uint64_t (&key)[W],
+                                             bool canon) {
+    bool take_rc = false, decided = !canon;
 #pragma unroll
     for (int i = 0; i < W; i++) {
         if (!decided && fw[i] != rc[i]) {

@@ -64,6 +64,7 @@ struct CountArgs {
     uint64_t n_bytes;     // k-mer windows must lie inside [0, n_bytes)
     const uint64_t* desc;
     uint32_t k, W, threshold, theta;
+    uint32_t canonical;   // 1: key = smaller of the k-mer and its reverse complement; 0: the k-mer (`-d`)
     uint64_t seed;
     // emergency area
     uint64_t* ovf_keys;   // [ovf_cap * W]

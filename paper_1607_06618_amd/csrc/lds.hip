@@ -502,7 +502,7 @@ __device__ void stage_count(const CountArgs& a, const LdsArgs& l, const Lds& s, 
         for (uint32_t j = 0; j < g.len; j++) {
             if (j) seg_step<W>(a.k, g);
             uint64_t key[W];
-            canonical_of<W>(g.fw, g.rc, key);
+            canonical_of<W>(g.fw, g.rc, key, a.canonical);
             const uint64_t h = key_hash<W>(key, a.seed);
             if (V > 1 && slice_of(h, V) != v) continue;
             atomicAdd(&hist[sub_of(h, P)], 1u);
@@ -603,7 +603,7 @@ __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s
                 for (int e = 0; e < R; e++) {
                     if ((uint32_t)e < g.len) {
                         if (e) seg_step<W>(a.k, g);
-                        canonical_of<W>(g.fw, g.rc, key[e]);
+                        canonical_of<W>(g.fw, g.rc, key[e], a.canonical);
                         const uint64_t h = key_hash<W>(key[e], a.seed);
                         if (V == 1 || slice_of(h, V) == v) {
                             sp[e] = sub_of(h, P);
@@ -690,7 +690,7 @@ __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s
 template <int W>
 __device__ __forceinline__ bool lds_insert(uint64_t* w0, uint64_t* rest, uint32_t* cnt, uint32_t C, uint32_t theta,
                                            const uint64_t (&key)[W], uint64_t h, uint32_t* status) {
-    if (W > 1 && key[0] == GERBIL_EMPTY) return false;
+    if (key[0] == GERBIL_EMPTY) return false;   // the empty-slot marker (an all-T word) is never stored
     // C is prime and 1 <= step < C: double hashing visits theta distinct slots.
     // The sub-table is chosen by the top bits of h's low half and the slice by
     // the top bits of its high half, so the slot and the step take bits 0-19

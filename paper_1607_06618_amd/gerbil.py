@@ -302,8 +302,8 @@ def make_params(k: int, m: int, n_bins: int, threshold: int, mode: int = GERBIL_
                 bin_map_ptr: int = 0, load_factor: float = 0.0, max_probes: int = 0, block: int = 0,
                 table: int = GERBIL_TABLE_AUTO, pool: int = 0, overflow_cap: int = 0, superm_cap: int = 0,
                 table_budget: int = 0, timing_events: int = 0, stage_clocks: int = 0,
-                size_sample: int = 0) -> gerbil_params:
-    return gerbil_params(k=k, m=m, n_bins=n_bins, threshold=threshold, canonical=1, order=order,
+                size_sample: int = 0, canonical: bool = True) -> gerbil_params:
+    return gerbil_params(k=k, m=m, n_bins=n_bins, threshold=threshold, canonical=int(canonical), order=order,
                          bin_map=bin_map_ptr or None, mode=mode, table=table, load_factor=load_factor,
                          max_probes=max_probes, block=block, pool=pool, overflow_cap=overflow_cap,
                          superm_cap=superm_cap, table_budget=table_budget, timing_events=timing_events or None,

@@ -60,11 +60,13 @@ def test_param_validation_before_launch():
         with pytest.raises(g.GerbilError) as e:
             g.gerbil_bin_workspace(enc, bad)
         assert e.value.status == g.GERBIL_EINVAL
+    # `-d` (no reverse-complement normalisation) is accepted; other values are not
+    assert g.gerbil_bin_workspace(enc, g.make_params(32, 7, 64, 2, canonical=False)) > 0
     p = g.make_params(32, 7, 64, 2)
-    p.canonical = 0
+    p.canonical = 2
     with pytest.raises(g.GerbilError) as e:
         g.gerbil_bin_workspace(enc, p)
-    assert e.value.status == g.GERBIL_EUNSUPPORTED
+    assert e.value.status == g.GERBIL_EINVAL
     # k must match the encoding
     with pytest.raises(g.GerbilError):
         g.gerbil_bin_workspace(enc, g.make_params(33, 7, 64, 2))
