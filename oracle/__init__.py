@@ -4,7 +4,9 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package. The GPU library never uses it.
 
 Thin ctypes wrapper over ``gerbil_oracle.c``; every function's arithmetic is
-in the C file, which cites the passages of the paper it follows.
+in the C file, which cites the passages of the paper it follows. The one
+exception is ``parse_reads`` (FASTA/FASTQ text to reads), written here in
+plain Python from the two formats' definitions.
 """
 from __future__ import annotations
 
@@ -231,3 +233,85 @@ def decode_key(key: np.ndarray, k: int) -> str:
         for j in range(nb):
             out.append("ACGT"[(w >> (2 * (nb - 1 - j))) & 3])
     return "".join(out)
+
+
+# ------------------------------------------------------------------ input parsing
+
+FASTQ, FASTA = 1, 2
+PARSE_EHEADER = 1    # FASTQ: a record's first line is empty or does not start with '@'
+PARSE_EPLUS = 2      # FASTQ: a record's third line does not start with '+'
+PARSE_EQUAL = 4      # FASTQ: quality and sequence lengths differ
+PARSE_ELINES = 8     # FASTQ: the number of lines is not a multiple of four
+PARSE_EORPHAN = 16   # FASTA: sequence bytes before the first header
+PARSE_EFORMAT = 128  # format to be detected, and the text starts with neither '@' nor '>'
+
+
+@dataclass
+class Parsed:
+    ascii: np.ndarray     # uint8: the reads back to back
+    offsets: np.ndarray   # uint64 [n_reads + 1]
+    status: int           # PARSE_* bits; the reads are defined only when it is 0
+    fmt: int              # FASTQ, FASTA, or 0 (empty text or undetected)
+    n_lines: int
+    n_bytes: int          # sequence bytes over every sequence line (also when status != 0)
+
+
+def parse_reads(text: bytes, fmt: int = 0) -> Parsed:
+    """Reads of a FASTA or FASTQ text (the input formats of App. C), as the
+    CSR arrays the encoder takes.
+
+    Lines end at a newline; a final line may lack one; one carriage return
+    right before a line's end is not part of the line. FASTQ records are four
+    lines (header starting with '@', sequence, a line starting with '+',
+    quality of the sequence's length) and each sequence line is one read.
+    FASTA: a non-empty line starting with '>' starts a read; every other line
+    is sequence and is appended to the current read (multi-line records).
+    Sequence bytes are kept as they are (the encoder decides which are
+    bases). fmt 0 detects the format from the first byte.
+    """
+    lines = text.split(b"\n")
+    if not text or text.endswith(b"\n"):
+        lines.pop()   # the piece after the final newline is not a line
+    n_lines = len(lines)
+    status = 0
+    if fmt == 0 and text:
+        fmt = FASTQ if text[:1] == b"@" else FASTA if text[:1] == b">" else 0
+        if fmt == 0:
+            status |= PARSE_EFORMAT
+
+    def body(line: bytes) -> bytes:
+        return line[:-1] if line.endswith(b"\r") else line
+
+    reads = []
+    n_bytes = 0
+    if fmt == FASTQ:
+        if n_lines % 4:
+            status |= PARSE_ELINES
+        for i in range(1, n_lines, 4):
+            head = lines[i - 1]
+            if not head.startswith(b"@"):
+                status |= PARSE_EHEADER
+            if i + 1 < n_lines and not lines[i + 1].startswith(b"+"):
+                status |= PARSE_EPLUS
+            seq = body(lines[i])
+            if i + 2 < n_lines and len(body(lines[i + 2])) != len(seq):
+                status |= PARSE_EQUAL
+            reads.append(seq)
+            n_bytes += len(seq)
+    elif fmt == FASTA:
+        for line in lines:
+            if line.startswith(b">"):
+                reads.append(bytearray())
+                continue
+            seq = body(line)
+            n_bytes += len(seq)
+            if not reads:
+                if seq:
+                    status |= PARSE_EORPHAN
+                continue
+            reads[-1] += seq
+    joined = b"".join(bytes(r) for r in reads)
+    offsets = np.zeros(len(reads) + 1, dtype=np.uint64)
+    if reads:
+        offsets[1:] = np.cumsum([len(r) for r in reads], dtype=np.uint64)
+    return Parsed(np.frombuffer(joined, dtype=np.uint8).copy(), offsets, status, fmt, n_lines, n_bytes)

@@ -196,3 +196,41 @@ def arrival_times(n_jobs: int, rate: float = SERVING_RATE) -> np.ndarray:
     """Poisson arrival times (seconds) of the serving stream."""
     gaps = [-math.log(1.0 - unit(SERVING_SEED, 101, j)) / rate for j in range(n_jobs)]
     return np.cumsum(np.array(gaps))
+
+
+# ------------------------------------------------------------ text renderings
+
+def to_fastq(ascii: np.ndarray, offsets: np.ndarray, seed: int = 1, crlf: bool = False) -> bytes:
+    """The reads as FASTQ text: Illumina-like header, sequence, '+', and a
+    random quality string over '!'..'J' (which includes '@', '>' and '+', so
+    a parser cannot take a line's first byte for its kind)."""
+    rng = np.random.default_rng(seed)
+    a = np.ascontiguousarray(ascii, dtype=np.uint8).tobytes()
+    o = np.asarray(offsets, dtype=np.int64)
+    n = o.size - 1
+    qual = rng.integers(33, 75, size=int(o[-1]) if n else 0, dtype=np.uint8).tobytes()
+    nl = b"\r\n" if crlf else b"\n"
+    parts = []
+    for r in range(n):
+        s, e = int(o[r]), int(o[r + 1])
+        parts.append(b"@SYN.%d %d/1 length=%d" % (r, r * 7 + 3, e - s) + nl + a[s:e] + nl + b"+" + nl + qual[s:e] + nl)
+    return b"".join(parts)
+
+
+def to_fasta(ascii: np.ndarray, offsets: np.ndarray, width: int = 60, crlf: bool = False,
+             blank_lines: bool = False) -> bytes:
+    """The reads as multi-line FASTA text, sequence lines of `width` bytes
+    (0: one line per read); blank_lines adds an empty line after each record."""
+    a = np.ascontiguousarray(ascii, dtype=np.uint8).tobytes()
+    o = np.asarray(offsets, dtype=np.int64)
+    nl = b"\r\n" if crlf else b"\n"
+    parts = []
+    for r in range(o.size - 1):
+        s, e = int(o[r]), int(o[r + 1])
+        parts.append(b">syn_%d some description" % r + nl)
+        step = width if width > 0 else max(1, e - s)
+        for x in range(s, e, step):
+            parts.append(a[x:min(e, x + step)] + nl)
+        if blank_lines:
+            parts.append(nl)
+    return b"".join(parts)

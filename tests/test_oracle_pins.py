@@ -15,6 +15,7 @@ import pytest
 from hypothesis import given, settings, strategies as st
 
 import oracle
+import synth
 from conftest import read_golden
 
 COMP = {"A": "T", "C": "G", "G": "C", "T": "A"}
@@ -355,3 +356,56 @@ def test_parallel_prefiltered_count_keys_matches_plain_count_keys(k):
     got = oracle.count_keys_parallel(a, o, k, query, threads=3)
     assert np.array_equal(got, want)
     assert (want > 0).sum() >= present.shape[0] // 2
+
+
+# ------------------------------------------------------------- input parsing
+
+def parsed_reads(p):
+    return [bytes(p.ascii[int(p.offsets[i]): int(p.offsets[i + 1])]) for i in range(p.offsets.size - 1)]
+
+
+def test_parse_hand_written_fasta():
+    text = b">r1 first\nACG\nTN\n>r2\n>r3\r\nGG\r\nca\r\n\n>r4\nA"
+    p = oracle.parse_reads(text)
+    assert p.fmt == oracle.FASTA and p.status == 0
+    assert parsed_reads(p) == [b"ACGTN", b"", b"GGca", b"A"]
+    assert p.n_lines == 10 and p.n_bytes == 10
+
+
+def test_parse_hand_written_fastq():
+    # quality lines that start with '@' and '+' are still quality lines
+    text = b"@a\nACGT\n+\n@@+!\n@b x\nNN\n+b x\n>+\n@c\n\n+\n\n"
+    p = oracle.parse_reads(text)
+    assert p.fmt == oracle.FASTQ and p.status == 0
+    assert parsed_reads(p) == [b"ACGT", b"NN", b""]
+    assert p.n_lines == 12
+
+
+def test_parse_errors():
+    assert oracle.parse_reads(b"").status == 0 and oracle.parse_reads(b"").offsets.tolist() == [0]
+    assert oracle.parse_reads(b"ACGT\n").status == oracle.PARSE_EFORMAT
+    assert oracle.parse_reads(b"@a\nAC\n+\nII\n@b\nAC\n").status == oracle.PARSE_ELINES
+    assert oracle.parse_reads(b"@a\nAC\n-\nII\n").status == oracle.PARSE_EPLUS
+    assert oracle.parse_reads(b"@a\nAC\n+\nIII\n").status == oracle.PARSE_EQUAL
+    assert oracle.parse_reads(b"@a\nAC\n+\nII\nb\nAC\n+\nII\n").status == oracle.PARSE_EHEADER
+    assert oracle.parse_reads(b"AC\n>a\nAC\n", fmt=oracle.FASTA).status == oracle.PARSE_EORPHAN
+    # blank lines before the first header are not orphans
+    assert oracle.parse_reads(b"\n\n>a\nAC\n", fmt=oracle.FASTA).status == 0
+
+
+@pytest.mark.parametrize("crlf", [False, True])
+def test_parse_round_trips_the_writers(crlf):
+    """The writers in the input generator and the parser are independent: a
+    rendering parses back to the reads it was made from."""
+    rng = random.Random(5)
+    reads = random_reads(rng, 300, 400) + [""]
+    a = np.frombuffer("".join(reads).encode(), dtype=np.uint8)
+    o = np.zeros(len(reads) + 1, dtype=np.uint64)
+    o[1:] = np.cumsum([len(r) for r in reads])
+    p = oracle.parse_reads(synth.to_fastq(a, o, seed=3, crlf=crlf))
+    assert p.status == 0 and p.fmt == oracle.FASTQ
+    assert np.array_equal(p.ascii, a) and np.array_equal(p.offsets, o)
+    for width, blank in ((60, False), (1, True), (0, False), (77, True)):
+        p = oracle.parse_reads(synth.to_fasta(a, o, width=width, crlf=crlf, blank_lines=blank))
+        assert p.status == 0 and p.fmt == oracle.FASTA
+        assert np.array_equal(p.ascii, a) and np.array_equal(p.offsets, o)
