@@ -49,6 +49,8 @@ def parse_args(argv=None):
     ap.add_argument("--serving", type=int, default=0, help="also serve this many jobs of the Poisson job stream")
     ap.add_argument("--serving-scale", type=float, default=1.0, help="genome-size scale of the served jobs")
     ap.add_argument("--serving-inflight", type=int, default=4)
+    ap.add_argument("--parse", action="store_true",
+                    help="also time FASTQ/FASTA parsing of the workload's reads on the device")
     return ap.parse_args(argv)
 
 
@@ -347,6 +349,8 @@ def main(argv=None):
         out["batched_over_plain"] = results["plain"]["wall"] / results["batched"]["wall"]
     if args.serving:
         out["serving"] = run_serving(args)
+    if args.parse:
+        out["parse"] = run_parse(args, ascii_, offsets)
     print(json.dumps(out), flush=True)
     return 0
 
@@ -380,6 +384,57 @@ def run_serving(args):
                   "k_mix": sorted({r.k for r in reqs})})
     print(f"[bench] serving: {stats}", file=sys.stderr, flush=True)
     return stats
+
+
+def run_parse(args, ascii_, offsets):
+    """Device parsing of the workload's reads rendered as FASTQ and as 60-column
+    FASTA: text in HBM -> CSR reads in HBM, timed with events on the stream
+    the parser runs on."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1607_06618_amd import gerbil as g
+
+    res = {}
+    renders = (("fastq", lambda: synth.to_fastq(ascii_, offsets, seed=9)),
+               ("fasta60", lambda: synth.to_fasta(ascii_, offsets, width=60)))
+    for name, render in renders:
+        text = render()
+        n = len(text)
+        text_d = torch.frombuffer(bytearray(text), dtype=torch.uint8).cuda()
+        del text
+        first = g.parse(text_d)   # sizes the line capacity
+        info = first.info
+        assert info.status == 0 and info.n_reads == offsets.size - 1 and info.n_bytes == int(offsets[-1])
+        cap = int(info.n_lines)
+        ws = torch.empty(g.gerbil_parse_workspace(n, cap), dtype=torch.uint8, device="cuda")
+        seq = torch.empty(n, dtype=torch.uint8, device="cuda")
+        offs = torch.empty(cap + 1, dtype=torch.int64, device="cuda")
+        info_d = torch.zeros(ctypes.sizeof(g.gerbil_parsed), dtype=torch.uint8, device="cuda")
+        s = torch.cuda.current_stream()
+        call = lambda: g.check("gerbil_parse", g.gerbil_parse(
+            text_d.data_ptr(), n, 0, ws.data_ptr(), ws.numel(), cap, seq.data_ptr(), n, offs.data_ptr(), cap,
+            info_d.data_ptr(), int(s.cuda_stream)))
+        for _ in range(2):
+            call()
+        reps = 20
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(s)
+        for _ in range(reps):
+            call()
+        e1.record(s)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        alg = n + int(info.n_bytes) + 8 * (int(info.n_reads) + 1)   # text read, reads written, offsets written
+        res[name] = {"text_bytes": n, "reads": int(info.n_reads), "lines": int(info.n_lines), "ms": round(ms, 4),
+                     "text_GBps": round(n / ms / 1e6, 1), "alg_GBps": round(alg / ms / 1e6, 1),
+                     "alg_frac_of_hbm_peak": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4)}
+        print(f"[bench] parse {name}: {res[name]}", file=sys.stderr, flush=True)
+        del text_d, ws, seq, offs, first
+        torch.cuda.empty_cache()
+    return res
 
 
 if __name__ == "__main__":

@@ -367,6 +367,59 @@ int32_t gerbil_records_workspace(uint64_t n, uint64_t* bytes);
 int32_t gerbil_records(const uint64_t* keys, const uint32_t* counts, uint64_t n, uint32_t k, void* ws,
                        uint64_t ws_bytes, uint8_t* out, uint64_t out_cap, uint64_t* out_bytes, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Input parsing (the formats of App. C): FASTA or FASTQ text in device
+ * memory to the CSR reads gerbil_encode takes.
+ * ------------------------------------------------------------------------ */
+
+enum { GERBIL_FORMAT_DETECT = 0, GERBIL_FORMAT_FASTQ = 1, GERBIL_FORMAT_FASTA = 2 };
+
+/* Status bits of a parse (gerbil_parsed.status); 0 = the reads are valid. */
+#define GERBIL_PARSE_EHEADER 0x001u  /* FASTQ: a record's first line is empty or lacks '@'        */
+#define GERBIL_PARSE_EPLUS 0x002u    /* FASTQ: a record's third line does not start with '+'     */
+#define GERBIL_PARSE_EQUAL 0x004u    /* FASTQ: quality and sequence lengths differ               */
+#define GERBIL_PARSE_ELINES 0x008u   /* FASTQ: line count not a multiple of four                 */
+#define GERBIL_PARSE_EORPHAN 0x010u  /* FASTA: sequence bytes before the first '>' header        */
+#define GERBIL_PARSE_EBYTES 0x020u   /* sequence bytes exceed seq_cap (nothing written past it)  */
+#define GERBIL_PARSE_EREADS 0x040u   /* reads exceed reads_cap (nothing written past it)         */
+#define GERBIL_PARSE_EFORMAT 0x080u  /* detection: the text starts with neither '@' nor '>'      */
+#define GERBIL_PARSE_ELINECAP 0x100u /* more lines than lines_cap: no read was produced          */
+
+typedef struct {
+    uint64_t n_reads;  /* reads found (FASTQ sequence lines, FASTA '>' headers)              */
+    uint64_t n_bytes;  /* sequence bytes over all sequence lines                              */
+    uint64_t n_lines;  /* lines of the text (a final line without a newline counts)          */
+    uint32_t status;   /* GERBIL_PARSE_* bits                                                  */
+    uint32_t format;   /* the format parsed (0: empty text or not detected)                   */
+} gerbil_parsed;
+
+/* Workspace bytes of gerbil_parse for n text bytes and up to lines_cap lines. */
+int32_t gerbil_parse_workspace(uint64_t n, uint64_t lines_cap, uint64_t* bytes);
+
+/* Parse FASTA or FASTQ text (the input formats named in App. C; compressed
+ * and staden inputs are not handled). Lines end at '\n'; a final line may
+ * lack it; one '\r' right before a line's end is dropped. FASTQ: records of
+ * four lines ('@' header, sequence, '+' line, quality of the sequence's
+ * length); each sequence line is one read. FASTA: a line starting with '>'
+ * starts a read and every other line is appended to the current read. Read
+ * bytes are copied unchanged; gerbil_encode decides which are bases.
+ *   text       device bytes [n], any alignment, n < 2^40
+ *   format     GERBIL_FORMAT_*; DETECT looks at the first byte ('@' or '>')
+ *   ws         device workspace of gerbil_parse_workspace(n, lines_cap) bytes,
+ *              256-byte aligned
+ *   seq        device bytes [seq_cap]: the reads back to back (seq_cap = n
+ *              always suffices)
+ *   offsets    device uint64 [reads_cap + 1]: read r is seq[offsets[r],
+ *              offsets[r+1])
+ *   out        device gerbil_parsed: counts and status, written by the parse
+ * Asynchronous on `stream`; the caller reads *out after synchronising. The
+ * reads are defined when out->status is 0; with EBYTES, EREADS or ELINECAP
+ * the counts in *out tell the capacities to call again with. Errors returned
+ * here: GERBIL_EINVAL (bad arguments or workspace), GERBIL_EDEVICE. */
+int32_t gerbil_parse(const uint8_t* text, uint64_t n, uint32_t format, void* ws, uint64_t ws_bytes,
+                     uint64_t lines_cap, uint8_t* seq, uint64_t seq_cap, uint64_t* offsets, uint64_t reads_cap,
+                     gerbil_parsed* out, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

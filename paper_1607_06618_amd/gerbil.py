@@ -30,6 +30,18 @@ GERBIL_ORDER_LEX = 1
 GERBIL_TABLE_AUTO = 0
 GERBIL_TABLE_HBM = 1
 GERBIL_TABLE_LDS = 2
+GERBIL_FORMAT_DETECT = 0
+GERBIL_FORMAT_FASTQ = 1
+GERBIL_FORMAT_FASTA = 2
+GERBIL_PARSE_EHEADER = 0x001
+GERBIL_PARSE_EPLUS = 0x002
+GERBIL_PARSE_EQUAL = 0x004
+GERBIL_PARSE_ELINES = 0x008
+GERBIL_PARSE_EORPHAN = 0x010
+GERBIL_PARSE_EBYTES = 0x020
+GERBIL_PARSE_EREADS = 0x040
+GERBIL_PARSE_EFORMAT = 0x080
+GERBIL_PARSE_ELINECAP = 0x100
 
 # device status bits (see gerbil_report.status)
 ST_OUT_CAP = 0x1
@@ -86,6 +98,10 @@ class gerbil_tune_result(ctypes.Structure):
                 ("best_ms", f32)]
 
 
+class gerbil_parsed(ctypes.Structure):
+    _fields_ = [("n_reads", u64), ("n_bytes", u64), ("n_lines", u64), ("status", u32), ("format", u32)]
+
+
 class GerbilError(RuntimeError):
     def __init__(self, fn: str, status: int, report: Optional[gerbil_report] = None):
         self.status = status
@@ -133,11 +149,13 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gerbil_autotune_reset.argtypes = []
     lib.gerbil_records_workspace.argtypes = [u64, P(u64)]
     lib.gerbil_records.argtypes = [vp, vp, u64, u32, vp, u64, vp, u64, vp, vp]
+    lib.gerbil_parse_workspace.argtypes = [u64, u64, P(u64)]
+    lib.gerbil_parse.argtypes = [vp, u64, u32, vp, u64, u64, vp, u64, vp, u64, vp, vp]
     for name in ("gerbil_encode_workspace", "gerbil_encode", "gerbil_bin_workspace", "gerbil_bin",
                  "gerbil_count_workspace", "gerbil_count", "gerbil_histogram", "gerbil_result",
                  "gerbil_graph_capture", "gerbil_graph_launch", "gerbil_graph_info", "gerbil_graph_destroy",
                  "gerbil_autotune_workspace", "gerbil_autotune", "gerbil_autotune_reset",
-                 "gerbil_records_workspace", "gerbil_records"):
+                 "gerbil_records_workspace", "gerbil_records", "gerbil_parse_workspace", "gerbil_parse"):
         getattr(lib, name).restype = ctypes.c_int32
     _lib = lib
     return lib
@@ -285,6 +303,53 @@ def records(keys_d, counts_d, n: int, k: int, stream=None):
         stream.synchronize()
     size = int(size_d.item())
     return out[:size]
+
+
+def gerbil_parse_workspace(n: int, lines_cap: int) -> int:
+    out = u64(0)
+    st = load().gerbil_parse_workspace(n, lines_cap, ctypes.byref(out))
+    if st:
+        raise GerbilError("gerbil_parse_workspace", st)
+    return out.value
+
+
+def gerbil_parse(text_ptr: int, n: int, fmt: int, ws_ptr: int, ws_bytes: int, lines_cap: int, seq_ptr: int,
+                 seq_cap: int, offsets_ptr: int, reads_cap: int, out_ptr: int, stream: int = 0) -> int:
+    return load().gerbil_parse(text_ptr or None, n, fmt, ws_ptr or None, ws_bytes, lines_cap, seq_ptr or None,
+                               seq_cap, offsets_ptr or None, reads_cap, out_ptr or None, stream)
+
+
+@dataclass
+class Parsed:
+    seq: "object"        # device uint8 [n_bytes]: the reads back to back
+    offsets: "object"    # device int64 [n_reads + 1]
+    info: gerbil_parsed  # counts, status, format
+
+
+def parse(text_d, fmt: int = GERBIL_FORMAT_DETECT, lines_cap: Optional[int] = None, stream=None) -> Parsed:
+    """FASTA/FASTQ text in a device uint8 tensor -> CSR reads on the device.
+
+    Starts from a guess of the line count and calls again with the exact
+    count when the guess was too small."""
+    import torch
+    n = int(text_d.numel())
+    dev = text_d.device
+    s = _stream_handle(stream)
+    cap = min(n + 1, lines_cap if lines_cap is not None else n // 32 + 1024)
+    info_d = torch.zeros(ctypes.sizeof(gerbil_parsed), dtype=torch.uint8, device=dev)
+    seq = torch.empty(max(1, n), dtype=torch.uint8, device=dev)
+    for _ in range(2):
+        ws = torch.empty(max(256, gerbil_parse_workspace(n, cap)), dtype=torch.uint8, device=dev)
+        offsets = torch.empty(cap + 1, dtype=torch.int64, device=dev)
+        check("gerbil_parse", gerbil_parse(text_d.data_ptr() if n else 0, n, fmt, ws.data_ptr(), ws.numel(), cap,
+                                           seq.data_ptr(), n, offsets.data_ptr(), cap, info_d.data_ptr(), s))
+        if stream is not None:
+            stream.synchronize()
+        info = gerbil_parsed.from_buffer_copy(info_d.cpu().numpy().tobytes())
+        if not (info.status & GERBIL_PARSE_ELINECAP):
+            break
+        cap = int(info.n_lines)
+    return Parsed(seq[: info.n_bytes], offsets[: info.n_reads + 1], info)
 
 
 def check(fn: str, status: int):

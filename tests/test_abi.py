@@ -135,3 +135,18 @@ def test_records_validation():
                 dict(ws_ptr=0), dict(ws_bytes=ws_need - 1), dict(ws_ptr=4096 + 8), dict(out_ptr=0)):
         args = dict(ok_args, **bad)
         assert g.gerbil_records(**args) == g.GERBIL_EINVAL, bad
+
+
+def test_parse_validation():
+    """Argument errors of the parser come back before any device call."""
+    ws = g.gerbil_parse_workspace(1000, 100)
+    assert ws >= 256
+    with pytest.raises(g.GerbilError):
+        g.gerbil_parse_workspace(1000, 1002)       # more lines than bytes + 1
+    fake = 4096
+    ok = dict(text_ptr=fake, n=1000, fmt=0, ws_ptr=fake, ws_bytes=ws, lines_cap=100, seq_ptr=fake, seq_cap=1000,
+              offsets_ptr=fake, reads_cap=100, out_ptr=fake)
+    for bad in (dict(text_ptr=0), dict(ws_ptr=0), dict(offsets_ptr=0), dict(out_ptr=0), dict(seq_ptr=0),
+                dict(fmt=3), dict(ws_bytes=ws - 1), dict(ws_ptr=fake + 16), dict(lines_cap=1002),
+                dict(n=1 << 40)):
+        assert g.gerbil_parse(**dict(ok, **bad)) == g.GERBIL_EINVAL, bad
