@@ -4,9 +4,10 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package. The GPU library never uses it.
 
 Thin ctypes wrapper over ``gerbil_oracle.c``; every function's arithmetic is
-in the C file, which cites the passages of the paper it follows. The one
-exception is ``parse_reads`` (FASTA/FASTQ text to reads), written here in
-plain Python from the two formats' definitions.
+in the C file, which cites the passages of the paper it follows. The
+exceptions, written here in plain Python from their definitions, are
+``parse_reads`` (FASTA/FASTQ text to reads) and ``order_table`` (the
+minimizer orders of Sec. 3.1 as rank tables).
 """
 from __future__ import annotations
 
@@ -58,7 +59,7 @@ def _load():
         lib.oracle_count_keys_range.restype = i32
         lib.oracle_encode.argtypes = [vp, vp, u64, u32, vp, vp, vp]
         lib.oracle_encode.restype = i32
-        lib.oracle_supermers.argtypes = [vp, vp, u64, u32, u32, u32, u32, vp, vp, vp, vp, vp, u64, vp]
+        lib.oracle_supermers.argtypes = [vp, vp, u64, u32, u32, u32, u32, vp, vp, vp, vp, vp, vp, u64, vp]
         lib.oracle_supermers.restype = i32
         lib.oracle_shard_of.argtypes = [vp, u32, u64]
         lib.oracle_shard_of.restype = u64
@@ -185,8 +186,9 @@ def encode(ascii: np.ndarray, offsets: np.ndarray, k: int):
 
 
 def supermers(ascii: np.ndarray, offsets: np.ndarray, k: int, m: int, n_bins: int, order: int = 0,
-              bin_map: Optional[np.ndarray] = None):
-    """Super-mers as a dict of arrays: start, n_kmers, bin, rank (in read order)."""
+              bin_map: Optional[np.ndarray] = None, rank_table: Optional[np.ndarray] = None):
+    """Super-mers as a dict of arrays: start, n_kmers, bin, rank (in read order).
+    order 2 ranks canonical m-mers by ``rank_table`` (see ``order_table``)."""
     lib = _load()
     a, o = _c(ascii, np.uint8), _c(offsets, np.uint64)
     cap = max(1, int(o[-1]))
@@ -196,9 +198,11 @@ def supermers(ascii: np.ndarray, offsets: np.ndarray, k: int, m: int, n_bins: in
     rank = np.empty(cap, dtype=np.uint64)
     n = np.zeros(1, dtype=np.uint64)
     bm = _c(bin_map, np.uint32) if bin_map is not None else None
+    rt = _c(rank_table, np.uint32) if rank_table is not None else None
     rc = lib.oracle_supermers(a.ctypes.data, o.ctypes.data, o.size - 1, k, m, order, n_bins,
-                              bm.ctypes.data if bm is not None else None, start.ctypes.data, nk.ctypes.data,
-                              b.ctypes.data, rank.ctypes.data, cap, n.ctypes.data)
+                              bm.ctypes.data if bm is not None else None, rt.ctypes.data if rt is not None else None,
+                              start.ctypes.data, nk.ctypes.data, b.ctypes.data, rank.ctypes.data, cap,
+                              n.ctypes.data)
     if rc != 0:
         raise RuntimeError(f"oracle_supermers failed with status {rc}")
     c = int(n[0])
@@ -315,3 +319,111 @@ def parse_reads(text: bytes, fmt: int = 0) -> Parsed:
     if reads:
         offsets[1:] = np.cumsum([len(r) for r in reads], dtype=np.uint64)
     return Parsed(np.frombuffer(joined, dtype=np.uint8).copy(), offsets, status, fmt, n_lines, n_bytes)
+
+
+# ------------------------------------------------------------ minimizer orders
+
+RANKS_KMC2, RANKS_LEX, RANKS_CGAT, RANKS_ROBERTS, RANKS_RANDOM, RANKS_DFP = 0, 1, 2, 3, 4, 5
+NOT_CANONICAL = 0xFFFFFFFF
+_BASES = "ACGT"
+_MASK64 = (1 << 64) - 1
+_GAMMA = 0x9E3779B97F4A7C15
+
+
+def splitmix64(seed: int, i: int) -> int:
+    """Output i (from 0) of the SplitMix64 generator seeded with `seed`
+    (Steele, Lea and Flood, 2014): the state advances by the golden-ratio
+    increment and each state value is passed through a fixed 64-bit mixer."""
+    z = (seed + (i + 1) * _GAMMA) & _MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK64
+    return z ^ (z >> 31)
+
+
+def mmer_string(code: int, m: int) -> str:
+    return "".join(_BASES[(code >> (2 * (m - 1 - i))) & 3] for i in range(m))
+
+
+def revcomp(s: str) -> str:
+    return s[::-1].translate(str.maketrans("ACGT", "TGCA"))
+
+
+def canonical_codes(m: int) -> list:
+    """Codes c of the m-mers that are their own canonical form (c <= rc(c))."""
+    return [c for c in range(4 ** m) if mmer_string(c, m) <= revcomp(mmer_string(c, m))]
+
+
+def mmer_frequencies(ascii: np.ndarray, offsets: np.ndarray, k: int, m: int, stride: int) -> dict:
+    """Sampled minimizer frequencies for dfp: the canonical m-mer that starts
+    each valid k-mer window whose global position is a multiple of `stride`."""
+    freq = {}
+    a = bytes(np.asarray(ascii, dtype=np.uint8))
+    o = [int(x) for x in offsets]
+    for r in range(len(o) - 1):
+        read = a[o[r]:o[r + 1]].decode("latin-1")
+        for i in range(len(read) - k + 1):
+            p = o[r] + i
+            if p % stride:
+                continue
+            win = read[i:i + k]
+            if not all(ch in "ACGTacgt" for ch in win):
+                continue
+            u = win[:m].upper()
+            c = min(u, revcomp(u))
+            code = 0
+            for ch in c:
+                code = 4 * code + _BASES.index(ch)
+            freq[code] = freq.get(code, 0) + 1
+    return freq
+
+
+def order_table(kind: int, m: int, seed: int = 0, pivot: float = 0.0, freq: Optional[dict] = None) -> np.ndarray:
+    """Rank of every canonical m-mer code under one of the orders of Sec. 3.1
+    (smaller rank = preferred minimizer); other codes get NOT_CANONICAL.
+
+    KMC2 and LEX: as in the super-mer oracle. CGAT: lexicographic with
+    C<G<A<T. ROBERTS: the bases at even positions (counting from 1) are
+    complemented, then lexicographic with C<A<T<G. RANDOM: canonical codes
+    sorted by the top 30 bits of SplitMix64 output number `code` (ties by
+    code); the rank is the position. DFP: canonical codes sorted by sampled
+    frequency (ties by code), then re-sorted by the distance of that position
+    from the pivot position floor(pivot * M), M = number of canonical codes
+    (ties: lower position first)."""
+    table = np.full(4 ** m, NOT_CANONICAL, dtype=np.uint32)
+    canon = canonical_codes(m)
+
+    def lex_rank(s, alphabet):
+        r = 0
+        for ch in s:
+            r = 4 * r + alphabet.index(ch)
+        return r
+
+    if kind in (RANKS_KMC2, RANKS_LEX, RANKS_CGAT, RANKS_ROBERTS):
+        for c in canon:
+            s = mmer_string(c, m)
+            if kind == RANKS_LEX:
+                r = c
+            elif kind == RANKS_KMC2:
+                r = c + (4 ** m if m >= 3 and s[:3] in ("AAA", "ACA") else 0)
+            elif kind == RANKS_CGAT:
+                r = lex_rank(s, "CGAT")
+            else:
+                t = "".join(revcomp(ch) if i % 2 == 1 else ch for i, ch in enumerate(s))
+                r = lex_rank(t, "CATG")
+            table[c] = r
+        return table
+    if kind == RANKS_RANDOM:
+        order = sorted(canon, key=lambda c: (splitmix64(seed, c) >> 34, c))
+        for pos, c in enumerate(order):
+            table[c] = pos
+        return table
+    if kind == RANKS_DFP:
+        freq = freq or {}
+        by_freq = sorted(canon, key=lambda c: (freq.get(c, 0), c))
+        M = len(canon)
+        P = int(float(np.float32(pivot)) * M)   # the pivot is a 32-bit float on both sides
+        by_dist = sorted(range(M), key=lambda pos: (abs(pos - P), pos))
+        for rank, pos in enumerate(by_dist):
+            table[by_freq[pos]] = rank
+        return table
+    raise ValueError(kind)

@@ -390,8 +390,10 @@ int oracle_encode(const uint8_t* ascii, const uint64_t* offsets, uint64_t n_read
 
 /* Rank of an m-mer string u under the chosen total order, using its
  * canonical form. order 0: KMC2-style (codes of canonical m-mers starting with
- * AAA or ACA are moved behind all others); order 1: plain lexicographic. The
- * canonical code is returned in *code. */
+ * AAA or ACA are moved behind all others); order 1: plain lexicographic;
+ * order 2: table[canonical code] (any order of Sec. 3.1 given as a table).
+ * The canonical code is returned in *code. */
+static const uint32_t* g_rank_table = NULL;
 static uint64_t mmer_rank(const char* u, uint32_t m, uint32_t order, uint64_t* code) {
     char v[64], c[64];
     reverse_complement(u, m, v);
@@ -399,6 +401,7 @@ static uint64_t mmer_rank(const char* u, uint32_t m, uint32_t order, uint64_t* c
     uint64_t x = 0;
     for (uint32_t j = 0; j < m; j++) x = (x << 2) | code2(c[j]);
     *code = x;
+    if (order == 2) return g_rank_table[x];
     if (order == 0 && m >= 3 && (memcmp(c, "AAA", 3) == 0 || memcmp(c, "ACA", 3) == 0))
         return x + (1ull << (2 * m));
     return x;
@@ -424,9 +427,10 @@ static uint64_t minimizer_rank(const char* s, uint32_t k, uint32_t m, uint32_t o
  */
 int oracle_supermers(const uint8_t* ascii, const uint64_t* offsets, uint64_t n_reads, uint32_t k, uint32_t m,
                      uint32_t order, uint32_t n_bins, const uint32_t* bin_map /* [4^m] or NULL */,
-                     uint64_t* start, uint32_t* n_kmers, uint32_t* bin, uint64_t* rank, uint64_t cap,
-                     uint64_t* n_out) {
-    if (m < 1 || m > 15 || m >= k || n_bins < 1) return ORACLE_EINVAL;
+                     const uint32_t* rank_table /* [4^m], order 2 */, uint64_t* start, uint32_t* n_kmers,
+                     uint32_t* bin, uint64_t* rank, uint64_t cap, uint64_t* n_out) {
+    if (m < 1 || m > 15 || m >= k || n_bins < 1 || order > 2 || (order == 2 && !rank_table)) return ORACLE_EINVAL;
+    g_rank_table = rank_table;
     char* s = (char*)malloc(k);
     uint64_t n = 0;
     int status = ORACLE_OK;

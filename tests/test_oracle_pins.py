@@ -409,3 +409,91 @@ def test_parse_round_trips_the_writers(crlf):
         p = oracle.parse_reads(synth.to_fasta(a, o, width=width, crlf=crlf, blank_lines=blank))
         assert p.status == 0 and p.fmt == oracle.FASTA
         assert np.array_equal(p.ascii, a) and np.array_equal(p.offsets, o)
+
+
+# ------------------------------------------------------------ minimizer orders
+
+def ranked_strings(table, m):
+    codes = [c for c in range(4 ** m) if table[c] != oracle.NOT_CANONICAL]
+    return [oracle.mmer_string(c, m) for c in sorted(codes, key=lambda c: int(table[c]))]
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 5, 6])
+def test_canonical_code_count(m):
+    # odd m: no m-mer is its own reverse complement; even m: 4^(m/2) are
+    expect = 4 ** m // 2 if m % 2 else (4 ** m + 2 ** m) // 2
+    assert len(oracle.canonical_codes(m)) == expect
+    t = oracle.order_table(oracle.RANKS_LEX, m)
+    assert sum(int(x) != oracle.NOT_CANONICAL for x in t) == expect
+
+
+def test_cgat_order_by_hand():
+    # C < G < A < T, first base first (Sec. 3.1)
+    assert ranked_strings(oracle.order_table(oracle.RANKS_CGAT, 2), 2) == \
+        ["CC", "CG", "CA", "GC", "GA", "AC", "AG", "AA", "AT", "TA"]
+
+
+def test_roberts_order_by_hand():
+    # the second base complemented, then C < A < T < G
+    assert ranked_strings(oracle.order_table(oracle.RANKS_ROBERTS, 2), 2) == \
+        ["CG", "CA", "CC", "AG", "AT", "AA", "AC", "TA", "GA", "GC"]
+    # the paper names CGCGCG as the kind of minimizer this order prefers
+    t = oracle.order_table(oracle.RANKS_ROBERTS, 6)
+    assert ranked_strings(t, 6)[0] == "CGCGCG"
+
+
+def test_splitmix64_published_outputs():
+    # the first three outputs of SplitMix64 from state 0
+    assert [oracle.splitmix64(0, i) for i in range(3)] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4,
+                                                          0x06C45D188009454F]
+
+
+@pytest.mark.parametrize("m", [3, 4, 7])
+def test_random_order_is_a_seeded_permutation(m):
+    canon = oracle.canonical_codes(m)
+    t1 = oracle.order_table(oracle.RANKS_RANDOM, m, seed=1)
+    t2 = oracle.order_table(oracle.RANKS_RANDOM, m, seed=2)
+    assert sorted(int(t1[c]) for c in canon) == list(range(len(canon)))
+    assert not np.array_equal(t1, t2)
+    # ranks follow the generator's values
+    keys = sorted((oracle.splitmix64(1, c) >> 34, c) for c in canon)
+    assert [int(t1[c]) for _, c in keys] == list(range(len(canon)))
+
+
+def test_dfp_by_hand():
+    # m = 1: canonical A and C; C is the rarer
+    f = {0: 5, 1: 3}
+    t0 = oracle.order_table(oracle.RANKS_DFP, 1, pivot=0.0, freq=f)
+    assert (int(t0[1]), int(t0[0])) == (0, 1)       # pivot 0: rare first
+    t1 = oracle.order_table(oracle.RANKS_DFP, 1, pivot=1.0, freq=f)
+    assert (int(t1[0]), int(t1[1])) == (0, 1)       # pivot 1: common first
+    # m = 2, no samples: frequency order is code order; pivot 0.5 of M = 10 is position 5
+    t = oracle.order_table(oracle.RANKS_DFP, 2, pivot=0.5, freq={})
+    canon = oracle.canonical_codes(2)
+    by_rank = sorted(canon, key=lambda c: int(t[c]))
+    assert [canon.index(c) for c in by_rank] == [5, 4, 6, 3, 7, 2, 8, 1, 9, 0]
+
+
+def test_dfp_frequency_sample_by_hand():
+    a = np.frombuffer(b"ACGTACxAC", dtype=np.uint8)
+    o = np.array([0, 6, 9], dtype=np.uint64)
+    # 3-windows of read 0 start with AC, CG, GT, TA; read 1 has no valid window
+    AC, CG, TA = 0b0001, 0b0110, 0b1100
+    assert oracle.mmer_frequencies(a, o, 3, 2, 1) == {AC: 2, CG: 1, TA: 1}
+    assert oracle.mmer_frequencies(a, o, 3, 2, 2) == {AC: 2}
+
+
+@pytest.mark.parametrize("kind,order", [(0, 0), (1, 1)])
+def test_table_order_reproduces_the_arithmetic_orders(kind, order):
+    """The table path of the super-mer oracle, fed the Python tables of KMC2
+    and LEX, gives the C oracle's own super-mers for those orders."""
+    rng = random.Random(77)
+    reads = random_reads(rng, 60, 200)
+    a = np.frombuffer("".join(reads).encode(), dtype=np.uint8)
+    o = np.zeros(len(reads) + 1, dtype=np.uint64)
+    o[1:] = np.cumsum([len(r) for r in reads])
+    for k, m in ((15, 5), (31, 7)):
+        ref = oracle.supermers(a, o, k, m, 37, order=order)
+        got = oracle.supermers(a, o, k, m, 37, order=2, rank_table=oracle.order_table(kind, m))
+        for key in ("start", "n_kmers", "bin", "rank"):
+            assert np.array_equal(ref[key], got[key]), key
