@@ -49,6 +49,8 @@ def parse_args(argv=None):
     ap.add_argument("--serving", type=int, default=0, help="also serve this many jobs of the Poisson job stream")
     ap.add_argument("--serving-scale", type=float, default=1.0, help="genome-size scale of the served jobs")
     ap.add_argument("--serving-inflight", type=int, default=4)
+    ap.add_argument("--orders", action="store_true",
+                    help="also compare the minimizer orders of Sec. 3.1 on the workload (super-mers, bins, step time)")
     ap.add_argument("--parse", action="store_true",
                     help="also time FASTQ/FASTA parsing of the workload's reads on the device")
     return ap.parse_args(argv)
@@ -349,6 +351,8 @@ def main(argv=None):
         out["batched_over_plain"] = results["plain"]["wall"] / results["batched"]["wall"]
     if args.serving:
         out["serving"] = run_serving(args)
+    if args.orders:
+        out["orders"] = run_orders(args, w, ascii_d, offsets_d, int(offsets[-1]), stream)
     if args.parse:
         out["parse"] = run_parse(args, ascii_, offsets)
     print(json.dumps(out), flush=True)
@@ -384,6 +388,67 @@ def run_serving(args):
                   "k_mix": sorted({r.k for r in reqs})})
     print(f"[bench] serving: {stats}", file=sys.stderr, flush=True)
     return stats
+
+
+def run_orders(args, w, ascii_d, offsets_d, n_bytes, stream):
+    """The analogue of the paper's Fig. 4 on this workload: for each minimizer
+    order, the super-mers (count and bases, the temporary data of the paper),
+    the largest bin in k-mers (what bounds a bin's table), and the batched
+    step time with that order."""
+    import torch
+
+    from paper_1607_06618_amd import gerbil as g
+
+    orders = [("kmc2", g.GERBIL_ORDER_KMC2, None), ("lex", g.GERBIL_ORDER_LEX, None),
+              ("cgat", g.GERBIL_ORDER_TABLE, (g.GERBIL_RANKS_CGAT, 0.0)),
+              ("roberts", g.GERBIL_ORDER_TABLE, (g.GERBIL_RANKS_ROBERTS, 0.0)),
+              ("random", g.GERBIL_ORDER_TABLE, (g.GERBIL_RANKS_RANDOM, 0.0))]
+    orders += [(f"dfp{p}", g.GERBIL_ORDER_TABLE, (g.GERBIL_RANKS_DFP, p)) for p in (0.0, 0.5, 0.8, 1.0)]
+    res = {}
+    with torch.cuda.stream(stream):
+        probe = g.Job(ascii_d, offsets_d, n_bytes, g.make_params(w.k, w.m, w.n_bins, w.threshold), stream=stream)
+        probe.encode()   # the dfp frequency sample is taken from this encoding
+        for name, order, spec in orders:
+            table_d, table_ms = None, 0.0
+            if spec is not None:
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                table_d = g.order_table(spec[0], w.m, seed=1, pivot=spec[1], enc=probe.enc, stream=stream)
+                e1.record(stream)
+                e1.synchronize()
+                table_ms = e0.elapsed_time(e1)
+            p = g.make_params(w.k, w.m, w.n_bins, w.threshold, mode=g.GERBIL_BATCHED, order=order,
+                              rank_table_ptr=table_d.data_ptr() if table_d is not None else 0)
+            job = g.Job(ascii_d, offsets_d, n_bytes, p, hist_len=65536, stream=stream)
+            job.encode()
+            job.bin()
+            st, rep = g.gerbil_result(job.enc, job.bins, None, g._stream_handle(stream))
+            n_sm = int(rep.n_superm)
+            off = int(job.bins.desc) - job.ws_bin.data_ptr()
+            desc = job.ws_bin[off: off + 8 * n_sm].view(torch.int64)
+            kmers = int((desc & 0xFFFFFF).sum().item())
+            koff = int(job.bins.bin_kmers) - job.ws_bin.data_ptr()
+            bin_kmers = job.ws_bin[koff: koff + 8 * w.n_bins].view(torch.int64)
+            job.prepare_count(n_valid=rep.n_valid)
+            job.run()
+            job.result()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.steps):
+                job.run()
+            e1.record(stream)
+            e1.synchronize()
+            r = job.result()
+            res[name] = {"superm": n_sm, "superm_bases": kmers + n_sm * (w.k - 1),
+                         "max_bin_kmers": int(bin_kmers.max().item()), "mean_bin_kmers": kmers / w.n_bins,
+                         "step_ms": round(e0.elapsed_time(e1) / args.steps, 3), "table_ms": round(table_ms, 3),
+                         "n_out": int(r.report.n_out)}
+            print(f"[bench] order {name}: {res[name]}", file=sys.stderr, flush=True)
+            job.close()
+            del job, table_d
+        probe.close()
+    torch.cuda.empty_cache()
+    return res
 
 
 def run_parse(args, ascii_, offsets):

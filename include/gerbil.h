@@ -70,8 +70,10 @@ enum { GERBIL_PLAIN = 0, GERBIL_BATCHED = 1 };
 
 /* Total order on minimizers (Sec. 3.1). KMC2: canonical m-mers in A<C<G<T
  * order with those starting AAA or ACA moved behind all others. LEX: plain
- * lexicographic order (Fig. 1). */
-enum { GERBIL_ORDER_KMC2 = 0, GERBIL_ORDER_LEX = 1 };
+ * lexicographic order (Fig. 1). TABLE: the rank of each canonical m-mer is
+ * read from gerbil_params.rank_table (made by gerbil_order_table for the
+ * other orders of Sec. 3.1, or by the caller); bin = rank mod n_bins. */
+enum { GERBIL_ORDER_KMC2 = 0, GERBIL_ORDER_LEX = 1, GERBIL_ORDER_TABLE = 2 };
 
 /* Where hash tables live. LDS (and AUTO): every bin, or hash slice of a large
  * bin, is split by key hash into sub-tables that one workgroup counts in LDS
@@ -118,6 +120,9 @@ typedef struct {
                                 still overflows, all of its keys take the emergency area, so
                                 results stay exact); 1 = count every k-mer; 0 = default 8       */
     uint32_t reserved0;
+    const uint32_t* rank_table; /* order TABLE: device uint32 [4^m], the rank of each canonical m-mer
+                                code (distinct ranks below 0xFFFFFFFF; entries of other codes are
+                                never read). bin_map must be NULL with this order.               */
 } gerbil_params;
 
 /* Output of gerbil_encode. All pointers point into the encode workspace. */
@@ -366,6 +371,43 @@ int32_t gerbil_records_workspace(uint64_t n, uint64_t* bytes);
  * workspace), GERBIL_EDEVICE (launch). */
 int32_t gerbil_records(const uint64_t* keys, const uint32_t* counts, uint64_t n, uint32_t k, void* ws,
                        uint64_t ws_bytes, uint8_t* out, uint64_t out_cap, uint64_t* out_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Minimizer orders (Sec. 3.1) as rank tables for GERBIL_ORDER_TABLE.
+ * ------------------------------------------------------------------------ */
+
+enum {
+    GERBIL_RANKS_KMC2 = 0,    /* the KMC2 order (also built into GERBIL_ORDER_KMC2)               */
+    GERBIL_RANKS_LEX = 1,     /* A<C<G<T (also built into GERBIL_ORDER_LEX)                        */
+    GERBIL_RANKS_CGAT = 2,    /* lexicographic with C<G<A<T                                        */
+    GERBIL_RANKS_ROBERTS = 3, /* Roberts et al.: bases at even positions (counting from 1)
+                                 complemented, then lexicographic with C<A<T<G                     */
+    GERBIL_RANKS_RANDOM = 4,  /* canonical m-mers sorted by the top 30 bits of SplitMix64 output
+                                 number `code` of `seed` (ties by code); rank = position          */
+    GERBIL_RANKS_DFP = 5      /* dfp(pivot): canonical m-mers sorted by sampled frequency (ties by
+                                 code), re-sorted by distance of the position from
+                                 floor(pivot * M), M = number of canonical m-mers (ties: lower
+                                 position first); rank = final position                          */
+};
+
+/* Workspace bytes of gerbil_order_table (0 for the orders without a sort). */
+int32_t gerbil_order_table_workspace(uint32_t kind, uint32_t m, uint64_t* bytes);
+
+/* Rank table of one minimizer order: table[c] is the rank of canonical m-mer
+ * code c; every other entry is 0xFFFFFFFF.
+ *   kind     GERBIL_RANKS_*; m in 1..15 (RANDOM and DFP: 1..12)
+ *   seed     RANDOM: generator seed
+ *   pivot    DFP: pivot factor in [0, 1]
+ *   stride, enc
+ *            DFP: the frequency sample is the canonical m-mer that starts
+ *            each valid k-mer window (gerbil_encode's bitmap, m < enc->k)
+ *            whose position is a multiple of stride (0 = 16)
+ *   ws       device workspace of gerbil_order_table_workspace bytes, 256-byte aligned
+ *   table    device uint32 [4^m]
+ * Asynchronous on `stream`. Errors: GERBIL_EINVAL, GERBIL_EDEVICE. */
+int32_t gerbil_order_table(uint32_t kind, uint32_t m, uint64_t seed, float pivot, uint32_t stride,
+                           const gerbil_encoded* enc, void* ws, uint64_t ws_bytes, uint32_t* table,
+                           hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Input parsing (the formats of App. C): FASTA or FASTQ text in device

@@ -120,7 +120,8 @@ int32_t check_params(const gerbil_params* p) {
     if (p->k < 2 || p->m < 1 || p->m > 15 || p->m >= p->k) return GERBIL_EINVAL;
     if (p->n_bins < 1 || p->n_bins > kMaxBins) return GERBIL_EINVAL;
     if (p->threshold < 1) return GERBIL_EINVAL;
-    if (p->order > 1 || p->mode > 1 || p->table > 2) return GERBIL_EINVAL;
+    if (p->order > GERBIL_ORDER_TABLE || p->mode > 1 || p->table > 2) return GERBIL_EINVAL;
+    if (p->order == GERBIL_ORDER_TABLE && (!p->rank_table || p->bin_map)) return GERBIL_EINVAL;
     // HBM tables hold every distinct key of a bin: at most 0.95 per slot. LDS
     // sub-tables are sized in k-mer occurrences, which repeat, so more than
     // one per slot can still fit (distinct keys beyond the slots go to the
@@ -534,6 +535,7 @@ int32_t gerbil_bin(const gerbil_encoded* enc, const gerbil_params* p, void* ws, 
     a.n_bins = p->n_bins;
     a.order = p->order;
     a.bin_map = p->bin_map;
+    a.rank_table = p->order == GERBIL_ORDER_TABLE ? p->rank_table : nullptr;
     a.cap = cap;
     a.list_cap = cap + kListSlack;
     a.list_desc = L.list_desc;

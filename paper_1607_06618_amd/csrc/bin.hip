@@ -20,6 +20,7 @@
 // boundaries; both pieces keep the same bin). Per-bin super-mer counts are
 // privatised in LDS. A scan and an LDS-privatised scatter then group the
 // descriptors by bin.
+#include "../../include/gerbil.h"
 #include "common.h"
 #include "internal.h"
 
@@ -30,8 +31,10 @@ constexpr uint32_t kMaxW = 256;                 // w = k - m + 1 <= 256 for k <=
 constexpr uint32_t kRankLen = kTile + kMaxW;    // ranks for positions P0-1 .. P0+kTile-1+w-1
 constexpr uint32_t kWordsPerTile = kTile / 64;
 
-__device__ __forceinline__ uint32_t rank_of(uint64_t fw, uint64_t rc, uint32_t m, uint32_t order) {
+__device__ __forceinline__ uint32_t rank_of(uint64_t fw, uint64_t rc, uint32_t m, uint32_t order,
+                                            const uint32_t* __restrict__ table) {
     uint64_t c = fw < rc ? fw : rc;
+    if (order == GERBIL_ORDER_TABLE) return table[c];
     if (order == 0 && m >= 3) {
         uint64_t head = c >> (2 * m - 6);
         if (head == 0 /* AAA */ || head == 4 /* ACA */) c += 1ull << (2 * m);
@@ -137,7 +140,7 @@ __global__ void __launch_bounds__(kBinBlock, 7) k_bin_tiles(BinArgs a) {
                     fw = ((fw << 2) | b2) & mmask;
                     rc = (rc >> 2) | ((3ull - b2) << (2 * a.m - 2));
                 }
-                R[i] = j < (int64_t)n_pos ? rank_of(fw, rc, a.m, a.order) : 0xFFFFFFFFu;
+                R[i] = j < (int64_t)n_pos ? rank_of(fw, rc, a.m, a.order, a.rank_table) : 0xFFFFFFFFu;
             }
             if (tid < kWordsPerTile) okS[tid] = f.ok;
         }

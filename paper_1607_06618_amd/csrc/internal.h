@@ -28,6 +28,7 @@ struct BinArgs {
     uint64_t n_bytes;
     uint32_t k, m, n_bins, order;
     const uint32_t* bin_map;
+    const uint32_t* rank_table;   // order TABLE: rank of each canonical m-mer code
     uint64_t cap;           // descriptors (super-mer pieces) that fit in desc
     uint64_t list_cap;      // cap + kListSlack: slots of the tile-order list, holes included
     uint64_t* list_desc;    // [list_cap] tile order

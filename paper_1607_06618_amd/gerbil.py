@@ -27,6 +27,13 @@ GERBIL_PLAIN = 0
 GERBIL_BATCHED = 1
 GERBIL_ORDER_KMC2 = 0
 GERBIL_ORDER_LEX = 1
+GERBIL_ORDER_TABLE = 2
+GERBIL_RANKS_KMC2 = 0
+GERBIL_RANKS_LEX = 1
+GERBIL_RANKS_CGAT = 2
+GERBIL_RANKS_ROBERTS = 3
+GERBIL_RANKS_RANDOM = 4
+GERBIL_RANKS_DFP = 5
 GERBIL_TABLE_AUTO = 0
 GERBIL_TABLE_HBM = 1
 GERBIL_TABLE_LDS = 2
@@ -60,7 +67,7 @@ class gerbil_params(ctypes.Structure):
                 ("order", u32), ("bin_map", vp), ("mode", u32), ("table", u32), ("load_factor", f32),
                 ("max_probes", u32), ("block", u32), ("pool", u32), ("overflow_cap", u64),
                 ("superm_cap", u64), ("table_budget", u64), ("timing_events", vp), ("stage_clocks", vp),
-                ("size_sample", u32), ("reserved0", u32)]
+                ("size_sample", u32), ("reserved0", u32), ("rank_table", vp)]
 
 
 class gerbil_encoded(ctypes.Structure):
@@ -150,12 +157,15 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gerbil_records_workspace.argtypes = [u64, P(u64)]
     lib.gerbil_records.argtypes = [vp, vp, u64, u32, vp, u64, vp, u64, vp, vp]
     lib.gerbil_parse_workspace.argtypes = [u64, u64, P(u64)]
+    lib.gerbil_order_table_workspace.argtypes = [u32, u32, P(u64)]
+    lib.gerbil_order_table.argtypes = [u32, u32, u64, f32, u32, P(gerbil_encoded), vp, u64, vp, vp]
     lib.gerbil_parse.argtypes = [vp, u64, u32, vp, u64, u64, vp, u64, vp, u64, vp, vp]
     for name in ("gerbil_encode_workspace", "gerbil_encode", "gerbil_bin_workspace", "gerbil_bin",
                  "gerbil_count_workspace", "gerbil_count", "gerbil_histogram", "gerbil_result",
                  "gerbil_graph_capture", "gerbil_graph_launch", "gerbil_graph_info", "gerbil_graph_destroy",
                  "gerbil_autotune_workspace", "gerbil_autotune", "gerbil_autotune_reset",
-                 "gerbil_records_workspace", "gerbil_records", "gerbil_parse_workspace", "gerbil_parse"):
+                 "gerbil_records_workspace", "gerbil_records", "gerbil_parse_workspace", "gerbil_parse",
+                 "gerbil_order_table_workspace", "gerbil_order_table"):
         getattr(lib, name).restype = ctypes.c_int32
     _lib = lib
     return lib
@@ -305,6 +315,37 @@ def records(keys_d, counts_d, n: int, k: int, stream=None):
     return out[:size]
 
 
+def gerbil_order_table_workspace(kind: int, m: int) -> int:
+    out = u64(0)
+    st = load().gerbil_order_table_workspace(kind, m, ctypes.byref(out))
+    if st:
+        raise GerbilError("gerbil_order_table_workspace", st)
+    return out.value
+
+
+def gerbil_order_table(kind: int, m: int, seed: int, pivot: float, stride: int, enc, ws_ptr: int, ws_bytes: int,
+                       table_ptr: int, stream: int = 0) -> int:
+    return load().gerbil_order_table(kind, m, seed, pivot, stride, ctypes.byref(enc) if enc is not None else None,
+                                     ws_ptr or None, ws_bytes, table_ptr or None, stream)
+
+
+def order_table(kind: int, m: int, seed: int = 0, pivot: float = 0.0, stride: int = 0, enc=None, device="cuda",
+                stream=None):
+    """Device rank table (uint32 [4^m], as an int32 tensor) of a minimizer order of Sec. 3.1."""
+    import torch
+    s = _stream_handle(stream)
+    table = torch.empty(4 ** m, dtype=torch.int32, device=device)
+    wsb = gerbil_order_table_workspace(kind, m)
+    ws = torch.empty(max(256, wsb), dtype=torch.uint8, device=device)
+    check("gerbil_order_table", gerbil_order_table(kind, m, seed, pivot, stride, enc, ws.data_ptr(), wsb,
+                                                   table.data_ptr(), s))
+    if stream is not None:
+        stream.synchronize()
+    else:
+        torch.cuda.current_stream().synchronize()
+    return table
+
+
 def gerbil_parse_workspace(n: int, lines_cap: int) -> int:
     out = u64(0)
     st = load().gerbil_parse_workspace(n, lines_cap, ctypes.byref(out))
@@ -367,12 +408,13 @@ def make_params(k: int, m: int, n_bins: int, threshold: int, mode: int = GERBIL_
                 bin_map_ptr: int = 0, load_factor: float = 0.0, max_probes: int = 0, block: int = 0,
                 table: int = GERBIL_TABLE_AUTO, pool: int = 0, overflow_cap: int = 0, superm_cap: int = 0,
                 table_budget: int = 0, timing_events: int = 0, stage_clocks: int = 0,
-                size_sample: int = 0, canonical: bool = True) -> gerbil_params:
+                size_sample: int = 0, canonical: bool = True, rank_table_ptr: int = 0) -> gerbil_params:
     return gerbil_params(k=k, m=m, n_bins=n_bins, threshold=threshold, canonical=int(canonical), order=order,
                          bin_map=bin_map_ptr or None, mode=mode, table=table, load_factor=load_factor,
                          max_probes=max_probes, block=block, pool=pool, overflow_cap=overflow_cap,
                          superm_cap=superm_cap, table_budget=table_budget, timing_events=timing_events or None,
-                         stage_clocks=stage_clocks or None, size_sample=size_sample)
+                         stage_clocks=stage_clocks or None, size_sample=size_sample,
+                         rank_table=rank_table_ptr or None)
 
 
 @dataclass

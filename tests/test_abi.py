@@ -150,3 +150,29 @@ def test_parse_validation():
                 dict(fmt=3), dict(ws_bytes=ws - 1), dict(ws_ptr=fake + 16), dict(lines_cap=1002),
                 dict(n=1 << 40)):
         assert g.gerbil_parse(**dict(ok, **bad)) == g.GERBIL_EINVAL, bad
+
+
+def test_order_table_validation():
+    assert g.gerbil_order_table_workspace(g.GERBIL_RANKS_CGAT, 15) == 0
+    assert g.gerbil_order_table_workspace(g.GERBIL_RANKS_RANDOM, 9) == 8 * 4 ** 9
+    assert g.gerbil_order_table_workspace(g.GERBIL_RANKS_DFP, 9) == 12 * 4 ** 9
+    for kind, m in ((6, 5), (0, 0), (0, 16), (g.GERBIL_RANKS_RANDOM, 13)):
+        with pytest.raises(g.GerbilError):
+            g.gerbil_order_table_workspace(kind, m)
+    fake = 4096
+    ws = g.gerbil_order_table_workspace(g.GERBIL_RANKS_DFP, 5)
+    enc = g.gerbil_encoded(n_reads=1, n_bytes=100, k=21, packed=fake, kmer_ok=fake)
+    ok = dict(kind=g.GERBIL_RANKS_DFP, m=5, seed=0, pivot=0.5, stride=0, enc=enc, ws_ptr=fake, ws_bytes=ws,
+              table_ptr=fake)
+    for bad in (dict(table_ptr=0), dict(ws_ptr=0), dict(ws_bytes=ws - 1), dict(pivot=1.5), dict(pivot=-0.1),
+                dict(enc=None), dict(m=21), dict(ws_ptr=fake + 8)):
+        assert g.gerbil_order_table(**dict(ok, **bad)) == g.GERBIL_EINVAL, bad
+    # the table order needs a table and no bin map
+    e = g.gerbil_encoded(n_reads=1, n_bytes=100, k=32)
+    with pytest.raises(g.GerbilError):
+        g.gerbil_bin_workspace(e, g.make_params(32, 7, 64, 2, order=g.GERBIL_ORDER_TABLE))
+    with pytest.raises(g.GerbilError):
+        g.gerbil_bin_workspace(e, g.make_params(32, 7, 64, 2, order=g.GERBIL_ORDER_TABLE, rank_table_ptr=fake,
+                                                bin_map_ptr=fake))
+    assert g.gerbil_bin_workspace(e, g.make_params(32, 7, 64, 2, order=g.GERBIL_ORDER_TABLE,
+                                                   rank_table_ptr=fake)) > 0

@@ -1,0 +1,122 @@
+"""Minimizer orders of Sec. 3.1 on the device: the rank tables against the
+oracle's (bit-exact), the super-mers of the table order against the oracle's
+super-mers for the same table, and counts that do not depend on the order.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import bin_arrays, make_job, random_reads, reads_to_csr
+from paper_1607_06618_amd import gerbil as g
+
+pytestmark = pytest.mark.gpu
+
+KINDS = [(g.GERBIL_RANKS_KMC2, "kmc2"), (g.GERBIL_RANKS_LEX, "lex"), (g.GERBIL_RANKS_CGAT, "cgat"),
+         (g.GERBIL_RANKS_ROBERTS, "roberts"), (g.GERBIL_RANKS_RANDOM, "random")]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    g.load()
+
+
+def host(table_d):
+    return table_d.cpu().numpy().view(np.uint32)
+
+
+def sample_reads(seed, n=200, lo=0, hi=600):
+    rng = np.random.default_rng(seed)
+    reads = random_reads(rng, n, lo, hi, n_rate=0.005, junk="N") + ["ACGT" * 300, "A" * 900, "CGCGCGCGTT" * 50]
+    return reads_to_csr(reads)
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 6, 7, 9])
+@pytest.mark.parametrize("kind,name", KINDS, ids=[n for _, n in KINDS])
+def test_rank_tables_match_the_oracle(kind, name, m):
+    got = host(g.order_table(kind, m, seed=12345))
+    want = oracle.order_table(kind, m, seed=12345)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("m,k,stride", [(2, 5, 1), (5, 21, 3), (7, 31, 16), (9, 65, 7)])
+@pytest.mark.parametrize("pivot", [0.0, 0.5, 0.8, 1.0])
+def test_dfp_tables_match_the_oracle(m, k, stride, pivot):
+    a, o = sample_reads(100 + m)
+    job = make_job(a, o, k, m=m)
+    job.encode()
+    got = host(g.order_table(g.GERBIL_RANKS_DFP, m, pivot=pivot, stride=stride, enc=job.enc))
+    want = oracle.order_table(oracle.RANKS_DFP, m, pivot=pivot, freq=oracle.mmer_frequencies(a, o, k, m, stride))
+    assert np.array_equal(got, want)
+
+
+def gpu_pieces(job):
+    desc, off, km = bin_arrays(job)
+    out = []
+    for b in range(job.bins.n_bins):
+        for d in desc[int(off[b]): int(off[b + 1])]:
+            out.append((int(d) >> 24, int(d) & 0xFFFFFF, b))
+    return sorted(out), km
+
+
+def oracle_pieces(a, o, k, m, nb, tile, table):
+    sm = oracle.supermers(a, o, k, m, nb, 2, rank_table=table)
+    out = []
+    for s, n, b in zip(sm["start"].tolist(), sm["n_kmers"].tolist(), sm["bin"].tolist()):
+        pos, end = s, s + n
+        while pos < end:   # the device cuts super-mers at tile edges
+            cut = min(end, (pos // tile + 1) * tile)
+            out.append((pos, cut - pos, b))
+            pos = cut
+    return sorted(out)
+
+
+ALL_KINDS = KINDS + [(g.GERBIL_RANKS_DFP, "dfp")]
+
+
+@pytest.mark.parametrize("k,m,nb", [(15, 5, 7), (33, 7, 64), (65, 9, 512)])
+@pytest.mark.parametrize("kind,name", ALL_KINDS, ids=[n for _, n in ALL_KINDS])
+def test_table_order_supermers_match_the_oracle(kind, name, k, m, nb):
+    a, o = sample_reads(k * 7 + m)
+    job = make_job(a, o, k, m=m, n_bins=nb)
+    job.encode()
+    table_d = g.order_table(kind, m, seed=99, pivot=0.5, stride=5, enc=job.enc)
+    job2 = make_job(a, o, k, m=m, n_bins=nb, order=g.GERBIL_ORDER_TABLE, rank_table_ptr=table_d.data_ptr())
+    job2.encode()
+    job2.bin()
+    st, rep = g.gerbil_result(job2.enc, job2.bins, None)
+    assert st == g.GERBIL_OK
+    got, km = gpu_pieces(job2)
+    assert got == oracle_pieces(a, o, k, m, nb, job2.bins.tile, host(table_d))
+    assert int(km.sum()) == rep.n_valid
+
+
+def test_kmc2_table_gives_the_builtin_kmc2_bins():
+    a, o = sample_reads(5)
+    k, m, nb = 41, 9, 97
+    table_d = g.order_table(g.GERBIL_RANKS_KMC2, m)
+    j1 = make_job(a, o, k, m=m, n_bins=nb, order=g.GERBIL_ORDER_KMC2)
+    j2 = make_job(a, o, k, m=m, n_bins=nb, order=g.GERBIL_ORDER_TABLE, rank_table_ptr=table_d.data_ptr())
+    for j in (j1, j2):
+        j.encode()
+        j.bin()
+    assert gpu_pieces(j1)[0] == gpu_pieces(j2)[0]
+
+
+@pytest.mark.parametrize("kind,name", ALL_KINDS, ids=[n for _, n in ALL_KINDS])
+@pytest.mark.parametrize("mode", [g.GERBIL_PLAIN, g.GERBIL_BATCHED])
+def test_counts_do_not_depend_on_the_order(kind, name, mode):
+    w = synth.CONFIGS["c2_k65"].scaled(0.001)
+    a, o = w.generate()
+    job = make_job(a, o, w.k, m=w.m)
+    job.encode()
+    table_d = g.order_table(kind, w.m, seed=3, pivot=0.8, enc=job.enc)
+    res = g.count_kmers(a, o, w.k, w.m, w.n_bins, w.threshold, 1024, mode=mode, order=g.GERBIL_ORDER_TABLE,
+                        rank_table_ptr=table_d.data_ptr())
+    ref = oracle.count(a, o, w.k, threshold=w.threshold)
+    keys, counts = res.sorted()
+    assert np.array_equal(keys, ref.keys) and np.array_equal(counts, ref.counts)
+    assert np.array_equal(res.hist, ref.folded_hist(1024))
