@@ -83,8 +83,9 @@ enum { GERBIL_TABLE_AUTO = 0, GERBIL_TABLE_HBM = 1, GERBIL_TABLE_LDS = 2 };
 
 /* Run parameters; mirrors the command line of App. A. Zero means default. */
 typedef struct {
-    uint32_t k;              /* k-mer length, 2 <= k <= 256 (App. A `-k`: 8..479; longer keys are
-                                GERBIL_EUNSUPPORTED)                                              */
+    uint32_t k;              /* k-mer length, 2 <= k <= 480 (App. A `-k`: 8..479). LDS tables take
+                                k <= 256; AUTO uses HBM tables above that, and TABLE_LDS with
+                                k > 256 is GERBIL_EUNSUPPORTED                                    */
     uint32_t m;              /* minimizer length, 1 <= m <= 15, m < k (App. A `-m`)              */
     uint32_t n_bins;         /* number of bins, 1..4096 (App. A `-f`, default 512)               */
     uint32_t threshold;      /* output iff count >= threshold, >= 1 (App. A `-l`, default 3)     */
@@ -201,7 +202,7 @@ int32_t gerbil_encode_workspace(uint64_t n_reads, uint64_t n_bytes, uint32_t k, 
  *            windows that contain it)
  *   offsets  device uint64 [n_reads+1]: read r is ascii[offsets[r], offsets[r+1]);
  *            offsets[0] = 0, non-decreasing, offsets[n_reads] = n_bytes
- *   k        window length (2..256)
+ *   k        window length (2..480)
  *   ws       device workspace of at least gerbil_encode_workspace() bytes,
  *            256-byte aligned
  *   out      host struct filled with pointers into ws

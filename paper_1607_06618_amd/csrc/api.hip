@@ -130,6 +130,7 @@ int32_t check_params(const gerbil_params* p) {
     if (p->load_factor < 0.0f || p->load_factor > max_load) return GERBIL_EINVAL;
     if (p->block && (p->block < 64 || p->block > 1024 || (p->block & 63))) return GERBIL_EINVAL;
     if (p->k > 32 * GERBIL_MAX_W) return GERBIL_EUNSUPPORTED;
+    if (p->table == GERBIL_TABLE_LDS && (p->k + 31) / 32 > GERBIL_MAX_LDS_W) return GERBIL_EUNSUPPORTED;
     if (p->canonical > 1) return GERBIL_EINVAL;
     return GERBIL_OK;
 }
@@ -193,7 +194,10 @@ uint32_t pool_size(const gerbil_params* p) {
     return std::min(q, p->n_bins);
 }
 float load_of(const gerbil_params* p) { return p->load_factor > 0 ? p->load_factor : kDefaultLoad; }
-bool use_lds(const gerbil_params* p) { return p->table != GERBIL_TABLE_HBM; }
+// AUTO takes LDS tables for keys of up to GERBIL_MAX_LDS_W words, HBM tables beyond
+bool use_lds(const gerbil_params* p) {
+    return p->table == GERBIL_TABLE_LDS || (p->table == GERBIL_TABLE_AUTO && (p->k + 31) / 32 <= GERBIL_MAX_LDS_W);
+}
 
 constexpr uint32_t kDefaultKeySlots = 8;
 constexpr uint32_t kDefaultLdsTheta = 64;   // single-slot probes are cheap in LDS

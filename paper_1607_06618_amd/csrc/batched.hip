@@ -218,6 +218,13 @@ hipError_t launch_count_persistent(const CountArgs& a, const PersistArgs& q, uin
         case 6: return persistent_w<6>(a, q, grid, s);
         case 7: return persistent_w<7>(a, q, grid, s);
         case 8: return persistent_w<8>(a, q, grid, s);
+        case 9: return persistent_w<9>(a, q, grid, s);
+        case 10: return persistent_w<10>(a, q, grid, s);
+        case 11: return persistent_w<11>(a, q, grid, s);
+        case 12: return persistent_w<12>(a, q, grid, s);
+        case 13: return persistent_w<13>(a, q, grid, s);
+        case 14: return persistent_w<14>(a, q, grid, s);
+        case 15: return persistent_w<15>(a, q, grid, s);
     }
     return hipErrorInvalidValue;
 }
@@ -246,6 +253,13 @@ uint32_t persistent_blocks_per_cu(uint32_t W, uint32_t block) {
         case 6: r = occupancy_w<6>(); break;
         case 7: r = occupancy_w<7>(); break;
         case 8: r = occupancy_w<8>(); break;
+        case 9: r = occupancy_w<9>(); break;
+        case 10: r = occupancy_w<10>(); break;
+        case 11: r = occupancy_w<11>(); break;
+        case 12: r = occupancy_w<12>(); break;
+        case 13: r = occupancy_w<13>(); break;
+        case 14: r = occupancy_w<14>(); break;
+        case 15: r = occupancy_w<15>(); break;
     }
     cached[W] = r;
     return r;

@@ -27,7 +27,7 @@
 namespace gerbil {
 
 constexpr uint32_t kBinBlock = 256;
-constexpr uint32_t kMaxW = 256;                 // w = k - m + 1 <= 256 for k <= 256
+constexpr uint32_t kMaxW = 32 * GERBIL_MAX_W;   // w = k - m + 1 <= k
 constexpr uint32_t kRankLen = kTile + kMaxW;    // ranks for positions P0-1 .. P0+kTile-1+w-1
 constexpr uint32_t kWordsPerTile = kTile / 64;
 

@@ -14,7 +14,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#define GERBIL_MAX_W 8          // longest key compiled: 8 words = k <= 256
+#define GERBIL_MAX_W 15         // longest key compiled: 15 words = k <= 480 (HBM tables)
+#define GERBIL_MAX_LDS_W 8      // LDS tables: keys of up to 8 words (k <= 256)
 #define GERBIL_EMPTY (~(uint64_t)0)    // probe word of an unclaimed slot
 
 // Device status bits (written with atomicOr, read back by the host).

@@ -180,6 +180,13 @@ hipError_t launch_count_bin(const CountArgs& a, const Table& t, uint32_t nb, uin
         case 6: return count_bin_w<6>(a, t, nb, d0, d1, block, s);
         case 7: return count_bin_w<7>(a, t, nb, d0, d1, block, s);
         case 8: return count_bin_w<8>(a, t, nb, d0, d1, block, s);
+        case 9: return count_bin_w<9>(a, t, nb, d0, d1, block, s);
+        case 10: return count_bin_w<10>(a, t, nb, d0, d1, block, s);
+        case 11: return count_bin_w<11>(a, t, nb, d0, d1, block, s);
+        case 12: return count_bin_w<12>(a, t, nb, d0, d1, block, s);
+        case 13: return count_bin_w<13>(a, t, nb, d0, d1, block, s);
+        case 14: return count_bin_w<14>(a, t, nb, d0, d1, block, s);
+        case 15: return count_bin_w<15>(a, t, nb, d0, d1, block, s);
     }
     return hipErrorInvalidValue;
 }
@@ -193,6 +200,13 @@ hipError_t launch_compact(const CountArgs& a, const Table& t, uint32_t nb, hipSt
         case 6: return compact_w<6>(a, t, nb, s);
         case 7: return compact_w<7>(a, t, nb, s);
         case 8: return compact_w<8>(a, t, nb, s);
+        case 9: return compact_w<9>(a, t, nb, s);
+        case 10: return compact_w<10>(a, t, nb, s);
+        case 11: return compact_w<11>(a, t, nb, s);
+        case 12: return compact_w<12>(a, t, nb, s);
+        case 13: return compact_w<13>(a, t, nb, s);
+        case 14: return compact_w<14>(a, t, nb, s);
+        case 15: return compact_w<15>(a, t, nb, s);
     }
     return hipErrorInvalidValue;
 }
@@ -206,6 +220,13 @@ hipError_t launch_overflow(const CountArgs& a, hipStream_t s) {
         case 6: return overflow_w<6>(a, s);
         case 7: return overflow_w<7>(a, s);
         case 8: return overflow_w<8>(a, s);
+        case 9: return overflow_w<9>(a, s);
+        case 10: return overflow_w<10>(a, s);
+        case 11: return overflow_w<11>(a, s);
+        case 12: return overflow_w<12>(a, s);
+        case 13: return overflow_w<13>(a, s);
+        case 14: return overflow_w<14>(a, s);
+        case 15: return overflow_w<15>(a, s);
     }
     return hipErrorInvalidValue;
 }

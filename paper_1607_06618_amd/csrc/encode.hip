@@ -138,7 +138,11 @@ __device__ __forceinline__ uint64_t ld_or_zero(const uint64_t* __restrict__ a, u
     return a[i < n ? i : n];
 }
 
-constexpr int kOkWords = 5;  // 64 output bits + up to 255 following bits
+// Words of G a thread reads: 64 output bits + k - 2 following bits. Five
+// words serve k <= 257, nine the longest keys (k <= 32 * GERBIL_MAX_W).
+constexpr int kOkWordsShort = 5;
+constexpr int kOkWordsLong = 9;
+static_assert((63 + 32 * GERBIL_MAX_W - 2) / 64 + 1 <= kOkWordsLong, "windows of the longest k");
 
 // Thread q computes bitmap word q: bit p = AND of G[p .. p+k-2], where
 // G[i] = valid[i] & valid[i+1] & !read_start[i+1] (i and i+1 are consecutive
@@ -146,6 +150,7 @@ constexpr int kOkWords = 5;  // 64 output bits + up to 255 following bits
 // rare (read ends and undetermined bases), so instead of ANDing shifted
 // copies the thread walks the zeros of G in [64q, 64q + 63 + k - 2] and
 // clears, for each zero z, the windows p in [z - k + 2, z] of its word.
+template <int kOkWords>
 __global__ void __launch_bounds__(256) k_kmer_ok(const uint64_t* __restrict__ valid, const uint64_t* __restrict__ rs,
                                                  uint64_t n_mask, uint32_t k, uint64_t* __restrict__ ok,
                                                  uint64_t* n_valid) {
@@ -158,7 +163,7 @@ __global__ void __launch_bounds__(256) k_kmer_ok(const uint64_t* __restrict__ va
             res = valid[q];
         } else {
             const uint32_t span = k - 2;                    // window p needs G[p .. p+span]
-            const uint32_t nw = (63 + span) / 64 + 1;       // words of G that can hold such zeros (<= 5)
+            const uint32_t nw = (63 + span) / 64 + 1;       // words of G that can hold such zeros (<= kOkWords)
             uint64_t V[kOkWords + 1], R[kOkWords + 1];
 #pragma unroll
             for (int i = 0; i <= kOkWords; i++) {
@@ -199,8 +204,12 @@ __global__ void __launch_bounds__(256) k_kmer_ok(const uint64_t* __restrict__ va
 hipError_t launch_kmer_ok(const uint64_t* valid, const uint64_t* read_start, uint64_t n_mask, uint32_t k,
                           uint64_t* kmer_ok, uint64_t* n_valid, hipStream_t s) {
     if (n_mask == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_kmer_ok, dim3(grid_for(n_mask, 256, 4096)), dim3(256), 0, s, valid, read_start, n_mask, k,
-                       kmer_ok, n_valid);
+    if ((63 + k - 2) / 64 + 1 <= (uint32_t)kOkWordsShort || k < 2)
+        hipLaunchKernelGGL(k_kmer_ok<kOkWordsShort>, dim3(grid_for(n_mask, 256, 4096)), dim3(256), 0, s, valid,
+                           read_start, n_mask, k, kmer_ok, n_valid);
+    else
+        hipLaunchKernelGGL(k_kmer_ok<kOkWordsLong>, dim3(grid_for(n_mask, 256, 4096)), dim3(256), 0, s, valid,
+                           read_start, n_mask, k, kmer_ok, n_valid);
     return hipGetLastError();
 }
 

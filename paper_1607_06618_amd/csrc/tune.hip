@@ -35,7 +35,7 @@ int quarter_octave(uint64_t x) { return x ? (int)floor(4.0 * log2((double)x)) : 
 std::vector<Candidate> candidates(const gerbil_params* p) {
     std::vector<Candidate> c;
     const bool batched = p->mode == GERBIL_BATCHED;
-    if (p->table != GERBIL_TABLE_HBM) {
+    if (p->table != GERBIL_TABLE_HBM && (p->k + 31) / 32 <= GERBIL_MAX_LDS_W) {
         const float fills[] = {0.6f, 0.8f, 1.0f, 1.2f};
         const uint32_t pools[] = {4, 8, 16};
         for (float f : fills) {

@@ -42,8 +42,9 @@ def test_encode_workspace_validation():
     assert g.gerbil_encode_workspace(10, 1000, 32) > 1000 // 4
     with pytest.raises(g.GerbilError):
         g.gerbil_encode_workspace(10, 1000, 1)
+    assert g.gerbil_encode_workspace(10, 1000, 480) > 1000 // 4   # keys of up to 15 words
     with pytest.raises(g.GerbilError):
-        g.gerbil_encode_workspace(10, 1000, 257)
+        g.gerbil_encode_workspace(10, 1000, 481)
 
 
 def test_param_validation_before_launch():
@@ -67,6 +68,14 @@ def test_param_validation_before_launch():
     with pytest.raises(g.GerbilError) as e:
         g.gerbil_bin_workspace(enc, p)
     assert e.value.status == g.GERBIL_EINVAL
+    # k above 256 takes HBM tables: AUTO picks them, LDS is refused
+    e300 = g.gerbil_encoded(n_reads=1, n_bytes=1000, k=300)
+    assert g.gerbil_bin_workspace(e300, g.make_params(300, 11, 64, 2)) > 0
+    with pytest.raises(g.GerbilError) as e:
+        g.gerbil_bin_workspace(e300, g.make_params(300, 11, 64, 2, table=g.GERBIL_TABLE_LDS))
+    assert e.value.status == g.GERBIL_EUNSUPPORTED
+    with pytest.raises(g.GerbilError) as e:
+        g.gerbil_bin_workspace(g.gerbil_encoded(n_reads=1, n_bytes=1000, k=481), g.make_params(481, 11, 64, 2))
     # k must match the encoding
     with pytest.raises(g.GerbilError):
         g.gerbil_bin_workspace(enc, g.make_params(33, 7, 64, 2))
@@ -131,7 +140,7 @@ def test_records_validation():
     size = ctypes.c_uint64(0)
     ok_args = dict(keys_ptr=fake, counts_ptr=fake, n=100, k=31, ws_ptr=4096, ws_bytes=ws_need, out_ptr=fake,
                    out_cap=1000, out_bytes_ptr=ctypes.addressof(size))
-    for bad in (dict(out_bytes_ptr=None), dict(k=0), dict(k=257), dict(keys_ptr=0), dict(counts_ptr=0),
+    for bad in (dict(out_bytes_ptr=None), dict(k=0), dict(k=481), dict(keys_ptr=0), dict(counts_ptr=0),
                 dict(ws_ptr=0), dict(ws_bytes=ws_need - 1), dict(ws_ptr=4096 + 8), dict(out_ptr=0)):
         args = dict(ok_args, **bad)
         assert g.gerbil_records(**args) == g.GERBIL_EINVAL, bad
