@@ -27,8 +27,12 @@
 namespace gerbil {
 
 constexpr uint32_t kBinBlock = 256;
-constexpr uint32_t kMaxW = 32 * GERBIL_MAX_W;   // w = k - m + 1 <= k
-constexpr uint32_t kRankLen = kTile + kMaxW;    // ranks for positions P0-1 .. P0+kTile-1+w-1
+// Longest window w = k - m + 1 a tile kernel serves: one instantiation for
+// w <= 256, one for the longest keys (the halo of ranks grows with w).
+constexpr uint32_t kMaxWShort = 256;
+constexpr uint32_t kMaxWLong = 32 * GERBIL_MAX_W;
+// ranks for positions P0-1 .. P0+kTile-1+w-1
+template <uint32_t MW> constexpr uint32_t rank_len() { return kTile + MW; }
 constexpr uint32_t kWordsPerTile = kTile / 64;
 
 __device__ __forceinline__ uint32_t rank_of(uint64_t fw, uint64_t rc, uint32_t m, uint32_t order,
@@ -42,11 +46,11 @@ __device__ __forceinline__ uint32_t rank_of(uint64_t fw, uint64_t rc, uint32_t m
     return (uint32_t)c;
 }
 
-constexpr uint32_t kRankPer = (kRankLen + kBinBlock - 1) / kBinBlock;     // ranks per thread
+template <uint32_t MW> constexpr uint32_t rank_per() { return (rank_len<MW>() + kBinBlock - 1) / kBinBlock; }
 constexpr uint32_t kMinPer = (kTile + 1 + kBinBlock - 1) / kBinBlock;      // minimizers per thread
 // The bases a thread's ranks need (kRankPer m-mers, m <= 15) start at most 31
 // bases into a packed word, so they lie in that word and the next.
-static_assert(31 + kRankPer - 1 + 15 <= 64, "a rank run must fit in two packed words");
+static_assert(31 + rank_per<kMaxWLong>() - 1 + 15 <= 64, "a rank run must fit in two packed words");
 static_assert(kWordsPerTile <= kBinBlock, "one bitmap word per thread");
 
 // Position of the n-th (from 0) set bit of x; x has more than n set bits.
@@ -70,11 +74,12 @@ struct TileFetch {
     uint64_t ok;       // threads < kWordsPerTile: one word of the valid-window bitmap
 };
 
+template <uint32_t MW>
 __device__ __forceinline__ TileFetch tile_fetch(const BinArgs& a, uint64_t tile, uint64_t n_tiles, uint64_t n_mask) {
     TileFetch f{0ull, 0ull, 0ull};
     if (tile >= n_tiles) return f;
     const int64_t P0 = (int64_t)(tile * kTile);
-    const int64_t j0 = P0 - 1 + (int64_t)(threadIdx.x * kRankPer);
+    const int64_t j0 = P0 - 1 + (int64_t)(threadIdx.x * rank_per<MW>());
     if (j0 < (int64_t)a.n_bytes) {   // j0 >= -1: word -1 is the zero pad; q + 1 <= n_words
         const int64_t q = j0 >> 5;
         f.w0 = a.packed[q];
@@ -93,8 +98,10 @@ __device__ __forceinline__ uint64_t pair_base(uint64_t w0, uint64_t w1, uint32_t
     return (w >> (62 - 2 * (o & 31))) & 3ull;
 }
 
+template <uint32_t MW>
 __global__ void __launch_bounds__(kBinBlock, 7) k_bin_tiles(BinArgs a) {
-    __shared__ uint32_t R[kRankLen];
+    constexpr uint32_t kRankPer = rank_per<MW>();
+    __shared__ uint32_t R[rank_len<MW>()];
     __shared__ uint32_t M[kTile + 1];
     __shared__ uint64_t brk[kWordsPerTile];
     __shared__ uint64_t stw[kWordsPerTile];
@@ -116,7 +123,7 @@ __global__ void __launch_bounds__(kBinBlock, 7) k_bin_tiles(BinArgs a) {
 
     for (uint32_t b = tid; b < a.n_bins; b += kBinBlock) bin_cnt[b] = 0;
 
-    TileFetch f = tile_fetch(a, blockIdx.x, n_tiles, n_mask);
+    TileFetch f = tile_fetch<MW>(a, blockIdx.x, n_tiles, n_mask);
     for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int64_t P0 = (int64_t)(tile * kTile);
         const uint32_t len = kTile + w;   // ranks R[i] for positions P0-1+i
@@ -145,7 +152,7 @@ __global__ void __launch_bounds__(kBinBlock, 7) k_bin_tiles(BinArgs a) {
             if (tid < kWordsPerTile) okS[tid] = f.ok;
         }
         // the next tile's loads are in flight while this one is processed
-        f = tile_fetch(a, tile + gridDim.x, n_tiles, n_mask);
+        f = tile_fetch<MW>(a, tile + gridDim.x, n_tiles, n_mask);
         __syncthreads();
         // 2. minimizer of the k-mer at P0-1+i = min R[i .. i+w): each thread takes
         //    a run of kMinPer positions; their windows share the middle part.
@@ -370,14 +377,22 @@ hipError_t launch_bin(const BinArgs& a, uint32_t max_grid, uint32_t cus, hipStre
     size_t sh_tiles = (size_t)a.n_bins * sizeof(uint32_t);
     // as many workgroups as are resident at once (a second, partial wave of
     // workgroups would double the time of a grid-stride kernel)
+    const uint32_t w = a.k - a.m + 1;
+    if (w > kMaxWLong) return hipErrorInvalidValue;
+    const bool shrt = w <= kMaxWShort;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bin_tiles, kBinBlock, sh_tiles) != hipSuccess ||
-        per_cu < 1)
-        per_cu = 1;
+    const hipError_t oe = shrt ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bin_tiles<kMaxWShort>,
+                                                                              kBinBlock, sh_tiles)
+                               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bin_tiles<kMaxWLong>,
+                                                                              kBinBlock, sh_tiles);
+    if (oe != hipSuccess || per_cu < 1) per_cu = 1;
     uint64_t grid = (uint64_t)cus * (uint32_t)per_cu;
     if (grid > max_grid) grid = max_grid;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_bin_tiles, dim3((uint32_t)grid), dim3(kBinBlock), sh_tiles, s, a);
+    if (shrt)
+        hipLaunchKernelGGL(k_bin_tiles<kMaxWShort>, dim3((uint32_t)grid), dim3(kBinBlock), sh_tiles, s, a);
+    else
+        hipLaunchKernelGGL(k_bin_tiles<kMaxWLong>, dim3((uint32_t)grid), dim3(kBinBlock), sh_tiles, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, a);
