@@ -49,6 +49,11 @@ def parse_args(argv=None):
     ap.add_argument("--serving", type=int, default=0, help="also serve this many jobs of the Poisson job stream")
     ap.add_argument("--serving-scale", type=float, default=1.0, help="genome-size scale of the served jobs")
     ap.add_argument("--serving-inflight", type=int, default=4)
+    ap.add_argument("--k", type=int, default=0, help="override the workload's k (keys above 256 bases use HBM tables)")
+    ap.add_argument("--non-canonical", action="store_true",
+                    help="count k-mers as read, without reverse-complement normalisation (-d)")
+    ap.add_argument("--records", action="store_true",
+                    help="also time the binary output records (App. C) of the step's pairs")
     ap.add_argument("--orders", action="store_true",
                     help="also compare the minimizer orders of Sec. 3.1 on the workload (super-mers, bins, step time)")
     ap.add_argument("--parse", action="store_true",
@@ -140,7 +145,7 @@ def percentile(xs, q):
     return s[i]
 
 
-def cpu_baseline(ascii_, offsets, k, threshold, target_s):
+def cpu_baseline(ascii_, offsets, k, threshold, target_s, canonical=True):
     """The oracle as it stands, single-threaded, on a leading sample of reads."""
     import numpy as np
 
@@ -149,14 +154,14 @@ def cpu_baseline(ascii_, offsets, k, threshold, target_s):
     # calibrate on a small sample, then size the timed sample to ~target_s
     n0 = min(n_reads, 2000)
     t = time.perf_counter()
-    r0 = oracle.count(ascii_, offsets[: n0 + 1], k, threshold=threshold)
+    r0 = oracle.count(ascii_, offsets[: n0 + 1], k, threshold=threshold, canonical=canonical)
     dt0 = max(1e-3, time.perf_counter() - t)
     per_window = dt0 / max(1, r0.n_valid)
     want_windows = target_s / per_window
     avg_windows = max(1.0, r0.n_valid / n0)
     n = int(min(n_reads, max(n0, want_windows / avg_windows)))
     t = time.perf_counter()
-    r = oracle.count(ascii_, offsets[: n + 1], k, threshold=threshold)
+    r = oracle.count(ascii_, offsets[: n + 1], k, threshold=threshold, canonical=canonical)
     dt = time.perf_counter() - t
     return {"value": r.n_valid / dt, "unit": "k-mers/s", "cores": 1, "kind": "oracle",
             "sample": f"first {n} of {n_reads} reads ({r.n_valid} valid windows), {dt:.1f} s single-threaded "
@@ -184,6 +189,10 @@ def main(argv=None):
     w = synth.CONFIGS[args.config]
     if args.scale != 1.0:
         w = w.scaled(args.scale)
+    if args.k:
+        import dataclasses
+        w = dataclasses.replace(w, k=args.k, name=f"{w.name}_k{args.k}",
+                                note=f"{w.note}; k overridden to {args.k}")
     t0 = time.perf_counter()
     ascii_, offsets = w.generate(threads=16)
     gen_s = time.perf_counter() - t0
@@ -211,7 +220,10 @@ def main(argv=None):
         mode = g.GERBIL_PLAIN if mode_name == "plain" else g.GERBIL_BATCHED
         ev = evs.pair()
         table = g.GERBIL_TABLE_LDS if args.table == "lds" else g.GERBIL_TABLE_HBM
+        if w.k > 256 and args.table == "lds":
+            table = g.GERBIL_TABLE_HBM   # LDS tables hold keys of up to 256 bases
         p = g.make_params(w.k, w.m, w.n_bins, w.threshold, mode=mode, pool=args.pool, load_factor=args.load, table=table,
+                          canonical=not args.non_canonical,
                           bin_map_ptr=bin_map_d.data_ptr() if bin_map_d is not None else 0,
                           timing_events=ctypes.addressof(ev))
         clocks_d = None
@@ -311,7 +323,8 @@ def main(argv=None):
     kname = {("batched", "lds"): "k_lds_persistent", ("plain", "lds"): "k_lds_stage",
              ("batched", "hbm"): "k_count_persistent", ("plain", "hbm"): "k_count_bin+k_compact"}[(head, head_table)]
     traffic = None
-    default_schedule = not args.tune and args.load == 0.0 and args.pool == 0 and args.scale == 1.0
+    default_schedule = (not args.tune and args.load == 0.0 and args.pool == 0 and args.scale == 1.0
+                        and not args.non_canonical)
     if default_schedule and "+" not in kname:
         traffic = measured_traffic(kname, w.name)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -321,7 +334,7 @@ def main(argv=None):
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(ascii_, offsets, w.k, w.threshold, args.cpu_seconds)
+        cpu = cpu_baseline(ascii_, offsets, w.k, w.threshold, args.cpu_seconds, canonical=not args.non_canonical)
 
     out = {
         "metric": METRIC, "value": value, "unit": "k-mers/s", "n_gpus": 1, "steps": args.steps,
@@ -331,7 +344,7 @@ def main(argv=None):
                    "threshold": w.threshold, "reads": int(offsets.size - 1), "bytes": int(ascii_.size),
                    "valid_windows": int(n_valid), "super_mers": int(rep.n_superm), "distinct": n_distinct,
                    "pairs_out": int(rep.n_out), "emergency_keys": int(rep.n_overflow), "schedule": head,
-                   "table": head_table},
+                   "table": head_table, "canonical": not args.non_canonical},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "p50_ms": percentile(R["step_ms"], 50), "p99_ms": percentile(R["step_ms"], 99),
@@ -351,6 +364,8 @@ def main(argv=None):
         out["batched_over_plain"] = results["plain"]["wall"] / results["batched"]["wall"]
     if args.serving:
         out["serving"] = run_serving(args)
+    if args.records:
+        out["records"] = run_records(R["job"], int(rep.n_out), w.k, stream)
     if args.orders:
         out["orders"] = run_orders(args, w, ascii_d, offsets_d, int(offsets[-1]), stream)
     if args.parse:
@@ -388,6 +403,39 @@ def run_serving(args):
                   "k_mix": sorted({r.k for r in reqs})})
     print(f"[bench] serving: {stats}", file=sys.stderr, flush=True)
     return stats
+
+
+def run_records(job, n: int, k: int, stream):
+    """The App. C record stream of the step's output pairs, timed with events
+    on the stream it runs on (pairs already in HBM; records written to HBM)."""
+    import torch
+
+    from paper_1607_06618_amd import gerbil as g
+
+    W, kb = (k + 31) // 32, (k + 3) // 4
+    with torch.cuda.stream(stream):
+        ws = torch.empty(max(256, g.gerbil_records_workspace(n)), dtype=torch.uint8, device="cuda")
+        cap = n * (5 + kb)
+        out = torch.empty(max(1, cap), dtype=torch.uint8, device="cuda")
+        size = torch.zeros(1, dtype=torch.int64, device="cuda")
+        call = lambda: g.check("gerbil_records", g.gerbil_records(
+            job.keys_d.data_ptr(), job.counts_d.data_ptr(), n, k, ws.data_ptr(), ws.numel(), out.data_ptr(), cap,
+            size.data_ptr(), int(stream.cuda_stream)))
+        call()
+        reps = 10
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            call()
+        e1.record(stream)
+        e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = int(size.item())
+    alg = n * (8 * W + 4) + nbytes   # pairs read once, records written once
+    res = {"pairs": n, "record_bytes": nbytes, "ms": round(ms, 4), "alg_GBps": round(alg / ms / 1e6, 1),
+           "alg_frac_of_hbm_peak": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4)}
+    print(f"[bench] records: {res}", file=sys.stderr, flush=True)
+    return res
 
 
 def run_orders(args, w, ascii_d, offsets_d, n_bytes, stream):
