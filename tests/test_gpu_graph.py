@@ -103,3 +103,44 @@ def test_graph_replays_follow_new_input_in_place():
             assert np.array_equal(hist, ref.folded_hist(256))
     finally:
         job.close()
+
+
+@pytest.mark.parametrize("variant", ["noncanonical", "cgat_table", "dfp_table"])
+def test_graph_replays_with_other_modes(variant):
+    """The `-d` mode and the rank-table orders replay from a graph exactly as
+    they run eagerly (the rank table is read at replay time)."""
+    import torch
+    w = synth.CONFIGS["c2_k65"].scaled(0.003)
+    a, o = w.generate()
+    canonical = variant != "noncanonical"
+    ref = oracle.count(a, o, w.k, threshold=w.threshold, canonical=canonical)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ad, od = to_device(a, o)
+    stream.synchronize()
+    table_d, kw = None, {}
+    if variant != "noncanonical":
+        probe = g.Job(ad, od, int(o[-1]), g.make_params(w.k, w.m, w.n_bins, w.threshold), stream=stream)
+        probe.encode()
+        kind = g.GERBIL_RANKS_CGAT if variant == "cgat_table" else g.GERBIL_RANKS_DFP
+        table_d = g.order_table(kind, w.m, pivot=0.5, enc=probe.enc, stream=stream)
+        kw = dict(order=g.GERBIL_ORDER_TABLE, rank_table_ptr=table_d.data_ptr())
+    p = g.make_params(w.k, w.m, w.n_bins, w.threshold, mode=g.GERBIL_BATCHED, canonical=canonical, **kw)
+    job = g.Job(ad, od, int(o[-1]), p, hist_len=512, stream=stream)
+    job.run()
+    eager = snapshot(job)
+    assert np.array_equal(eager[0], ref.keys) and np.array_equal(eager[1], ref.counts)
+    try:
+        job.capture()
+        for rep in range(2):
+            with torch.cuda.stream(stream):
+                job.keys_d.fill_(-1)
+                job.counts_d.fill_(0)
+                job.hist_d.fill_(7)
+            stream.synchronize()
+            job.replay()
+            got = snapshot(job)
+            for x, y in zip(eager, got):
+                assert np.array_equal(x, y), f"replay {rep} differs from the eager run"
+    finally:
+        job.close()
