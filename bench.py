@@ -54,6 +54,8 @@ def parse_args(argv=None):
                     help="count k-mers as read, without reverse-complement normalisation (-d)")
     ap.add_argument("--records", action="store_true",
                     help="also time the binary output records (App. C) of the step's pairs")
+    ap.add_argument("--estimator", action="store_true",
+                    help="also evaluate the distinct-k-mer estimate of the paper's table sizing on the workload's bins")
     ap.add_argument("--orders", action="store_true",
                     help="also compare the minimizer orders of Sec. 3.1 on the workload (super-mers, bins, step time)")
     ap.add_argument("--parse", action="store_true",
@@ -368,6 +370,14 @@ def main(argv=None):
         out["records"] = run_records(R["job"], int(rep.n_out), w.k, stream)
     if args.orders:
         out["orders"] = run_orders(args, w, ascii_d, offsets_d, int(offsets[-1]), stream)
+    if args.estimator:
+        # the step's buffers are no longer needed: the threshold-1 count holds every distinct key
+        for r in results.values():
+            r["job"] = None
+        shared_out.clear()
+        R = None
+        torch.cuda.empty_cache()
+        out["estimator"] = run_estimator(args, w, ascii_d, offsets_d, int(offsets[-1]), stream, cap=n_distinct + 1)
     if args.parse:
         out["parse"] = run_parse(args, ascii_, offsets)
     print(json.dumps(out), flush=True)
@@ -435,6 +445,56 @@ def run_records(job, n: int, k: int, stream):
     res = {"pairs": n, "record_bytes": nbytes, "ms": round(ms, 4), "alg_GBps": round(alg / ms / 1e6, 1),
            "alg_frac_of_hbm_peak": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4)}
     print(f"[bench] records: {res}", file=sys.stderr, flush=True)
+    return res
+
+
+def run_estimator(args, w, ascii_d, offsets_d, n_bytes, stream, cap=None):
+    """The table-size estimate of Sec. 3.4.1 on this workload's bins: the
+    distinct k-mers of a bin predicted as its k-mers times the ratio of
+    distinct to all k-mers over the bins counted before it (bins in index
+    order, the first predicted with ratio 1), against the true distinct
+    k-mers per bin (a count with threshold 1, every key mapped to its bin)."""
+    import numpy as np
+    import torch
+
+    from paper_1607_06618_amd import gerbil as g
+
+    with torch.cuda.stream(stream):
+        p = g.make_params(w.k, w.m, w.n_bins, 1, mode=g.GERBIL_BATCHED, canonical=not args.non_canonical)
+        job = g.Job(ascii_d, offsets_d, n_bytes, p, hist_len=65536, stream=stream, cap=cap)
+        job.run()
+        st, rep = g.gerbil_result(job.enc, job.bins, job.state, g._stream_handle(stream))
+        if st != g.GERBIL_OK:
+            raise g.GerbilError("gerbil_result", st, rep)
+        n = int(rep.n_out)
+        bins = g.key_bins(job.keys_d, n, job.p, stream=stream)
+        distinct = torch.bincount(bins, minlength=w.n_bins).cpu().numpy().astype(np.float64)
+        koff = int(job.bins.bin_kmers) - job.ws_bin.data_ptr()
+        kmers = job.ws_bin[koff: koff + 8 * w.n_bins].view(torch.int64).cpu().numpy().astype(np.float64)
+    del job, bins
+    torch.cuda.empty_cache()
+    assert int(distinct.sum()) == n
+    used = kmers > 0
+    ratio = distinct[used] / kmers[used]
+    cum_d = np.concatenate([[0.0], np.cumsum(distinct)[:-1]])
+    cum_k = np.concatenate([[0.0], np.cumsum(kmers)[:-1]])
+    run_ratio = np.where(cum_k > 0, cum_d / np.maximum(cum_k, 1.0), 1.0)
+    pred = kmers * run_ratio
+    sel = used & (np.arange(w.n_bins) > 0) & (distinct > 0)
+    rel = (pred[sel] - distinct[sel]) / distinct[sel]
+    glob = float(distinct.sum() / kmers.sum())
+    rel_static = (kmers[sel] * glob - distinct[sel]) / distinct[sel]
+    res = {"distinct": n, "kmers": int(kmers.sum()), "global_ratio": round(glob, 4),
+           "bin_ratio_min_median_max": [round(float(x), 4) for x in (ratio.min(), np.median(ratio), ratio.max())],
+           "running_estimate_abs_rel_err_median_p95_max": [round(float(x), 4) for x in
+                                                           (np.median(np.abs(rel)), np.percentile(np.abs(rel), 95),
+                                                            np.abs(rel).max())],
+           "running_estimate_under_5pct_bins": int((rel < -0.05).sum()),
+           "running_estimate_under_10pct_bins": int((rel < -0.10).sum()),
+           "global_ratio_abs_rel_err_median_max": [round(float(np.median(np.abs(rel_static))), 4),
+                                                   round(float(np.abs(rel_static).max()), 4)],
+           "bins": int(sel.sum())}
+    print(f"[bench] estimator: {res}", file=sys.stderr, flush=True)
     return res
 
 

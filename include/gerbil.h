@@ -373,6 +373,16 @@ int32_t gerbil_records_workspace(uint64_t n, uint64_t* bytes);
 int32_t gerbil_records(const uint64_t* keys, const uint32_t* counts, uint64_t n, uint32_t k, void* ws,
                        uint64_t ws_bytes, uint8_t* out, uint64_t out_cap, uint64_t* out_bytes, hipStream_t stream);
 
+/* Bin of each of n keys (the layout gerbil_count emits) under the binning of
+ * `p` (k, m, n_bins, order, bin_map, rank_table): the bin that gerbil_bin
+ * sends every occurrence of the key to (Sec. 2.1, Sec. 3.1). With counts of
+ * every key (threshold 1) this gives the distinct k-mers of each bin, the
+ * quantity the table-size estimate of Sec. 3.4.1 predicts.
+ *   keys   device uint64 [n * W];  bins  device uint32 [n]
+ * Asynchronous on `stream`. Errors: GERBIL_EINVAL, GERBIL_EUNSUPPORTED, GERBIL_EDEVICE. */
+int32_t gerbil_key_bins(const uint64_t* keys, uint64_t n, const gerbil_params* p, uint32_t* bins,
+                        hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Minimizer orders (Sec. 3.1) as rank tables for GERBIL_ORDER_TABLE.
  * ------------------------------------------------------------------------ */

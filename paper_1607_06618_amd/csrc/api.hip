@@ -230,21 +230,16 @@ LdsSizing lds_sizing(const gerbil_params* p, uint64_t n_bytes) {
     return z;
 }
 
-// Keys a slot must hold: the largest rank (bin, or hash slice of a bin) with
-// slack for hash variance, plus the margins of its sampled run capacities:
-// with S the sampling step and L its segment length, N keys in P runs, the
-// capacities add up to at most N + 4 sqrt(S L N) (error of the sampled
-// total) + 4 sqrt(S L) sqrt(P (N + P L)) (sum of the per-run margins, by
-// Cauchy-Schwarz) + 32 P.
+// Keys a slot must hold: the k-mers of the largest bin, plus the margins of
+// its sampled run capacities: with S the sampling step and L its segment
+// length, N keys in P runs, the capacities add up to at most N + 4 sqrt(S L N)
+// (error of the sampled total) + 4 sqrt(S L) sqrt(P (N + P L)) (sum of the
+// per-run margins, by Cauchy-Schwarz) + 32 P. A hash slice of a large bin is
+// bounded by the whole bin only: slices split distinct keys evenly, but a
+// key's occurrences all go to one slice, so repeats can load one slice with
+// most of the bin.
 uint64_t lds_slot_keys(uint64_t max_kmers, const LdsSizing& z) {
-    const uint64_t per_slice = (uint64_t)kLdsMaxSub * z.target;
-    uint64_t V = (max_kmers + per_slice - 1) / per_slice;
-    double N;
-    if (V <= 1) {
-        N = (double)std::max<uint64_t>(max_kmers, 1);
-    } else {
-        N = std::min((double)max_kmers / (double)V * 1.25 + 65536.0, (double)max_kmers);
-    }
+    const double N = (double)std::max<uint64_t>(max_kmers, 1);
     if (z.sample <= 1) return (uint64_t)N;
     const double S = z.sample;
     double P = std::ceil(N / z.target);
@@ -772,3 +767,17 @@ int32_t gerbil_result(const gerbil_encoded* enc, const gerbil_bins* bins, const 
 }
 
 }  // extern "C"
+
+extern "C" int32_t gerbil_key_bins(const uint64_t* keys, uint64_t n, const gerbil_params* p, uint32_t* bins,
+                                   hipStream_t stream) {
+    if (check_params(p) != GERBIL_OK) return check_params(p);
+    if (n && (!keys || !bins)) return GERBIL_EINVAL;
+    BinArgs a{};
+    a.k = p->k;
+    a.m = p->m;
+    a.n_bins = p->n_bins;
+    a.order = p->order;
+    a.bin_map = p->bin_map;
+    a.rank_table = p->order == GERBIL_ORDER_TABLE ? p->rank_table : nullptr;
+    return launch_key_bins(keys, n, a, bins, stream) == hipSuccess ? GERBIL_OK : GERBIL_EDEVICE;
+}

@@ -373,6 +373,44 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_scatter(BinArgs a) {
     }
 }
 
+// Bin of each key, as the tile kernel assigns it: the smallest rank over the
+// k-m+1 canonical m-mers of the k-mer the key encodes, then bin_map or
+// rank mod n_bins. (A key's m-mers are those of every window that holds it,
+// on either strand, so the bin is the one its occurrences went to.)
+__global__ void __launch_bounds__(256) k_key_bins(const uint64_t* __restrict__ keys, uint64_t n, uint32_t k,
+                                                  uint32_t W, uint32_t m, uint32_t order,
+                                                  const uint32_t* __restrict__ rank_table,
+                                                  const uint32_t* __restrict__ bin_map, uint32_t n_bins,
+                                                  uint32_t* __restrict__ bins) {
+    const uint64_t mmask = (1ull << (2 * m)) - 1ull;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
+        const uint64_t* key = keys + i * W;
+        uint64_t fw = 0, rc = 0;
+        uint32_t best = 0xFFFFFFFFu, p = 0;
+        for (uint32_t w = 0; w < W; w++) {
+            const uint64_t x = key[w];
+            const uint32_t r = w + 1 < W ? 32u : k - 32u * (W - 1);   // bases in this word, right-aligned
+            for (uint32_t o = 0; o < r; o++, p++) {
+                const uint64_t b = (x >> (2 * (r - 1 - o))) & 3ull;
+                fw = ((fw << 2) | b) & mmask;
+                rc = (rc >> 2) | ((3ull - b) << (2 * m - 2));
+                if (p + 1 >= m) best = min(best, rank_of(fw, rc, m, order, rank_table));
+            }
+        }
+        uint32_t bin = bin_map ? bin_map[best & (uint32_t)mmask] : best % n_bins;
+        if (bin >= n_bins) bin = n_bins - 1;   // defensive, as in the tile kernel
+        bins[i] = bin;
+    }
+}
+
+hipError_t launch_key_bins(const uint64_t* keys, uint64_t n, const BinArgs& a, uint32_t* bins, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const uint64_t g = (n + 255) / 256;
+    hipLaunchKernelGGL(k_key_bins, dim3((uint32_t)(g < 65536 ? g : 65536)), dim3(256), 0, s, keys, n, a.k,
+                       (a.k + 31) / 32, a.m, a.order, a.rank_table, a.bin_map, a.n_bins, bins);
+    return hipGetLastError();
+}
+
 hipError_t launch_bin(const BinArgs& a, uint32_t max_grid, uint32_t cus, hipStream_t s) {
     size_t sh_tiles = (size_t)a.n_bins * sizeof(uint32_t);
     // as many workgroups as are resident at once (a second, partial wave of

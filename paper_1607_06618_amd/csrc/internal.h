@@ -43,6 +43,8 @@ struct BinArgs {
     uint32_t* status;
 };
 hipError_t launch_bin(const BinArgs& a, uint32_t max_grid, uint32_t cus, hipStream_t s);
+// bins[i] = the bin gerbil_bin gives key i (uses a.k, a.m, a.order, a.rank_table, a.bin_map, a.n_bins)
+hipError_t launch_key_bins(const uint64_t* keys, uint64_t n, const BinArgs& a, uint32_t* bins, hipStream_t s);
 // The tile kernel hands out list slots to each workgroup in chunks of at
 // least kListChunk and fills them without gaps; only the unused end of each
 // workgroup's last chunk (under kListChunk slots) is a hole. At most

@@ -158,6 +158,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gerbil_records.argtypes = [vp, vp, u64, u32, vp, u64, vp, u64, vp, vp]
     lib.gerbil_parse_workspace.argtypes = [u64, u64, P(u64)]
     lib.gerbil_order_table_workspace.argtypes = [u32, u32, P(u64)]
+    lib.gerbil_key_bins.argtypes = [vp, u64, P(gerbil_params), vp, vp]
     lib.gerbil_order_table.argtypes = [u32, u32, u64, f32, u32, P(gerbil_encoded), vp, u64, vp, vp]
     lib.gerbil_parse.argtypes = [vp, u64, u32, vp, u64, u64, vp, u64, vp, u64, vp, vp]
     for name in ("gerbil_encode_workspace", "gerbil_encode", "gerbil_bin_workspace", "gerbil_bin",
@@ -165,7 +166,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                  "gerbil_graph_capture", "gerbil_graph_launch", "gerbil_graph_info", "gerbil_graph_destroy",
                  "gerbil_autotune_workspace", "gerbil_autotune", "gerbil_autotune_reset",
                  "gerbil_records_workspace", "gerbil_records", "gerbil_parse_workspace", "gerbil_parse",
-                 "gerbil_order_table_workspace", "gerbil_order_table"):
+                 "gerbil_order_table_workspace", "gerbil_order_table", "gerbil_key_bins"):
         getattr(lib, name).restype = ctypes.c_int32
     _lib = lib
     return lib
@@ -313,6 +314,18 @@ def records(keys_d, counts_d, n: int, k: int, stream=None):
         stream.synchronize()
     size = int(size_d.item())
     return out[:size]
+
+
+def gerbil_key_bins(keys_ptr: int, n: int, params: gerbil_params, bins_ptr: int, stream: int = 0) -> int:
+    return load().gerbil_key_bins(keys_ptr or None, n, ctypes.byref(params), bins_ptr or None, stream)
+
+
+def key_bins(keys_d, n: int, params: gerbil_params, stream=None):
+    """Bin of each of the first n device keys under `params`' binning (device int32 tensor)."""
+    import torch
+    bins = torch.empty(max(1, n), dtype=torch.int32, device=keys_d.device)
+    check("gerbil_key_bins", gerbil_key_bins(keys_d.data_ptr(), n, params, bins.data_ptr(), _stream_handle(stream)))
+    return bins[:n]
 
 
 def gerbil_order_table_workspace(kind: int, m: int) -> int:

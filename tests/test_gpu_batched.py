@@ -137,3 +137,18 @@ def test_batched_overflow_capacity_error():
     job.run()
     st, rep = g.gerbil_result(job.enc, job.bins, job.state)
     assert st == g.GERBIL_ECAPACITY and rep.status & g.ST_OVF_CAP
+
+
+@pytest.mark.parametrize("mode", [g.GERBIL_PLAIN, B])
+def test_sliced_bin_with_one_dominant_key(mode):
+    """A bin large enough to be cut into hash slices, whose k-mers are nearly
+    all one key: that key's occurrences all land in one slice, so the key
+    slots must hold the whole bin (a slice is not bounded by its share)."""
+    k, L, n = 65, 300, 35000
+    reads = ["A" * L] * n + ["T" * L] * n   # one canonical key, A^65, in one bin
+    a, o = reads_to_csr(reads)
+    res = g.count_kmers(a, o, k, 9, 16, 1, 64, mode=mode, table=g.GERBIL_TABLE_LDS)
+    expect = 2 * n * (L - k + 1)
+    assert res.report.n_valid == expect
+    keys, counts = res.sorted()
+    assert keys.shape == (1, 3) and keys[0].tolist() == [0, 0, 0] and counts.tolist() == [expect]

@@ -120,3 +120,36 @@ def test_counts_do_not_depend_on_the_order(kind, name, mode):
     keys, counts = res.sorted()
     assert np.array_equal(keys, ref.keys) and np.array_equal(counts, ref.counts)
     assert np.array_equal(res.hist, ref.folded_hist(1024))
+
+
+@pytest.mark.parametrize("order", ["kmc2", "lex", "roberts_table"])
+@pytest.mark.parametrize("k,m,nb", [(25, 7, 37), (65, 9, 512), (300, 11, 64)])
+def test_key_bins_match_the_oracle(order, k, m, nb):
+    """The bin of every emitted key is the bin of the one super-mer that the
+    key, read as a sequence of its own, forms in the oracle."""
+    import torch
+    a, o = sample_reads(k + m + nb, n=80, lo=k, hi=k + 400)
+    table_d, kw = None, {}
+    if order == "roberts_table":
+        table_d = g.order_table(g.GERBIL_RANKS_ROBERTS, m)
+        kw = dict(order=g.GERBIL_ORDER_TABLE, rank_table_ptr=table_d.data_ptr())
+    else:
+        kw = dict(order=g.GERBIL_ORDER_KMC2 if order == "kmc2" else g.GERBIL_ORDER_LEX)
+    job = make_job(a, o, k, m=m, n_bins=nb, threshold=1, **kw)
+    job.run()
+    res = job.result()
+    n = res.counts.size
+    bins = g.key_bins(job.keys_d, n, job.p).cpu().numpy()
+    rank_table = host(table_d) if table_d is not None else None
+    oorder = 2 if table_d is not None else (0 if order == "kmc2" else 1)
+    rng = np.random.default_rng(k)
+    for i in rng.choice(n, size=min(n, 600), replace=False):
+        s = oracle.decode_key(res.keys[i], k).encode()
+        sm = oracle.supermers(np.frombuffer(s, dtype=np.uint8), np.array([0, k], dtype=np.uint64), k, m, nb, oorder,
+                              rank_table=rank_table)
+        assert sm["bin"].size == 1
+        assert int(bins[i]) == int(sm["bin"][0]), (i, s)
+    # every key's occurrences went to its bin: per-bin k-mer totals agree
+    per_bin = np.bincount(bins, weights=res.counts.astype(np.float64), minlength=nb)
+    _, off, km = bin_arrays(job)
+    assert np.array_equal(per_bin.astype(np.int64), km.astype(np.int64))
