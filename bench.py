@@ -471,6 +471,15 @@ def run_estimator(args, w, ascii_d, offsets_d, n_bytes, stream, cap=None):
         distinct = torch.bincount(bins, minlength=w.n_bins).cpu().numpy().astype(np.float64)
         koff = int(job.bins.bin_kmers) - job.ws_bin.data_ptr()
         kmers = job.ws_bin[koff: koff + 8 * w.n_bins].view(torch.int64).cpu().numpy().astype(np.float64)
+        # HyperLogLog sketches of the same bins, from the k-mer occurrences (no counting)
+        log2_regs = 12
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        regs = g.hll_registers(job, log2_regs, stream=stream)
+        e1.record(stream)
+        e1.synchronize()
+        hll_ms = e0.elapsed_time(e1)
+        regs = regs.cpu().numpy()
     del job, bins
     torch.cuda.empty_cache()
     assert int(distinct.sum()) == n
@@ -484,6 +493,13 @@ def run_estimator(args, w, ascii_d, offsets_d, n_bytes, stream, cap=None):
     rel = (pred[sel] - distinct[sel]) / distinct[sel]
     glob = float(distinct.sum() / kmers.sum())
     rel_static = (kmers[sel] * glob - distinct[sel]) / distinct[sel]
+    mreg = regs.shape[1]
+    alpha = 0.7213 / (1.0 + 1.079 / mreg)
+    hll = alpha * mreg * mreg / (2.0 ** -regs.astype(np.float64)).sum(axis=1)
+    zeros = (regs == 0).sum(axis=1)
+    small = (hll <= 2.5 * mreg) & (zeros > 0)
+    hll[small] = mreg * np.log(mreg / zeros[small])   # linear counting
+    rel_hll = (hll[sel] - distinct[sel]) / distinct[sel]
     res = {"distinct": n, "kmers": int(kmers.sum()), "global_ratio": round(glob, 4),
            "bin_ratio_min_median_max": [round(float(x), 4) for x in (ratio.min(), np.median(ratio), ratio.max())],
            "running_estimate_abs_rel_err_median_p95_max": [round(float(x), 4) for x in
@@ -493,6 +509,12 @@ def run_estimator(args, w, ascii_d, offsets_d, n_bytes, stream, cap=None):
            "running_estimate_under_10pct_bins": int((rel < -0.10).sum()),
            "global_ratio_abs_rel_err_median_max": [round(float(np.median(np.abs(rel_static))), 4),
                                                    round(float(np.abs(rel_static).max()), 4)],
+           "hll_registers_per_bin": mreg,
+           "hll_abs_rel_err_median_p95_max": [round(float(x), 4) for x in
+                                              (np.median(np.abs(rel_hll)), np.percentile(np.abs(rel_hll), 95),
+                                               np.abs(rel_hll).max())],
+           "hll_under_5pct_bins": int((rel_hll < -0.05).sum()),
+           "hll_ms": round(hll_ms, 2),
            "bins": int(sel.sum())}
     print(f"[bench] estimator: {res}", file=sys.stderr, flush=True)
     return res

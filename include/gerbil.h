@@ -383,6 +383,20 @@ int32_t gerbil_records(const uint64_t* keys, const uint32_t* counts, uint64_t n,
 int32_t gerbil_key_bins(const uint64_t* keys, uint64_t n, const gerbil_params* p, uint32_t* bins,
                         hipStream_t stream);
 
+/* HyperLogLog sketch of the distinct k-mers of every bin, from the k-mer
+ * occurrences of its super-mers: the alternative to the ratio estimate of
+ * Sec. 3.4.1 (it needs no counting). Register j of bin b is the largest
+ * rank of the first set bit, after the top log2_regs bits, of the 64-bit
+ * hash of a key whose top bits are j (the usual HyperLogLog update); the
+ * estimate is formed by the caller.
+ *   bins       the output of gerbil_bin (its workspace still valid)
+ *   p          the parameters the bins were made with (k, canonical)
+ *   log2_regs  4..15 registers per bin as a power of two
+ *   regs       device uint32 [n_bins << log2_regs], every register written
+ * Asynchronous on `stream`. Errors: GERBIL_EINVAL, GERBIL_EUNSUPPORTED, GERBIL_EDEVICE. */
+int32_t gerbil_hll_bins(const gerbil_bins* bins, const gerbil_params* p, uint32_t log2_regs, uint32_t* regs,
+                        hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Minimizer orders (Sec. 3.1) as rank tables for GERBIL_ORDER_TABLE.
  * ------------------------------------------------------------------------ */

@@ -781,3 +781,16 @@ extern "C" int32_t gerbil_key_bins(const uint64_t* keys, uint64_t n, const gerbi
     a.rank_table = p->order == GERBIL_ORDER_TABLE ? p->rank_table : nullptr;
     return launch_key_bins(keys, n, a, bins, stream) == hipSuccess ? GERBIL_OK : GERBIL_EDEVICE;
 }
+
+extern "C" int32_t gerbil_hll_bins(const gerbil_bins* bins, const gerbil_params* p, uint32_t log2_regs,
+                                   uint32_t* regs, hipStream_t stream) {
+    const int32_t st = check_params(p);
+    if (st) return st;
+    if (!bins || !regs || p->k != bins->k || p->n_bins != bins->n_bins) return GERBIL_EINVAL;
+    if (log2_regs < 4 || log2_regs > 15) return GERBIL_EINVAL;
+    if (!bins->desc || !bins->bin_off || !bins->packed) return GERBIL_EINVAL;
+    return launch_hll(bins->packed, bins->n_bytes, bins->desc, bins->bin_off, bins->n_bins, p->k, p->canonical,
+                      log2_regs, regs, stream) == hipSuccess
+               ? GERBIL_OK
+               : GERBIL_EDEVICE;
+}

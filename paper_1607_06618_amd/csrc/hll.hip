@@ -1,0 +1,86 @@
+// HyperLogLog sketches of the distinct k-mers of every bin, from the k-mer
+// occurrences of its super-mers: the alternative the table-size estimate
+// of Sec. 3.4.1 is compared with. One workgroup per bin keeps the bin's 2^p
+// registers in LDS; each thread walks one super-mer, hashes every canonical
+// key and raises register (top p bits of the hash) to the rank of the first
+// set bit of the remaining bits; the registers are written out once.
+#include "../../include/gerbil.h"
+#include "common.h"
+#include "internal.h"
+
+namespace gerbil {
+namespace {
+
+constexpr uint32_t kHllBlock = 256;
+constexpr uint64_t kHllSeed = 0x5bd1e9955bd1e995ull;   // not the table seed: an independent hash
+
+template <int W>
+__global__ void __launch_bounds__(kHllBlock) k_hll(const uint64_t* __restrict__ packed, uint64_t n_bytes,
+                                                   const uint64_t* __restrict__ desc,
+                                                   const uint64_t* __restrict__ bin_off, uint32_t n_bins, uint32_t k,
+                                                   uint32_t canonical, uint32_t p, uint32_t* __restrict__ regs) {
+    extern __shared__ uint32_t R[];   // [2^p]
+    const uint32_t m = 1u << p;
+    for (uint32_t b = blockIdx.x; b < n_bins; b += gridDim.x) {
+        for (uint32_t j = threadIdx.x; j < m; j += kHllBlock) R[j] = 0;
+        __syncthreads();
+        const uint64_t d1 = bin_off[b + 1];
+        for (uint64_t d = bin_off[b] + threadIdx.x; d < d1; d += kHllBlock) {
+            const uint64_t dd = desc[d];
+            const int64_t start = (int64_t)(dd >> 24);
+            const uint32_t nk = (uint32_t)(dd & 0xFFFFFFu);
+            if (nk == 0 || start < 0 || (uint64_t)start + nk - 1 + k > n_bytes) continue;   // never read out of range
+            for (uint32_t t = 0; t < nk; t++) {
+                uint64_t fw[W], rc[W], key[W];
+                extract_kmer<W>(packed, start + t, k, fw, rc);
+                canonical_of<W>(fw, rc, key, canonical);
+                const uint64_t h = key_hash<W>(key, kHllSeed);
+                const uint32_t idx = (uint32_t)(h >> (64 - p));
+                const uint32_t rho = (uint32_t)__clzll((h << p) | (1ull << (p - 1))) + 1u;
+                atomicMax(&R[idx], rho);
+            }
+        }
+        __syncthreads();
+        for (uint32_t j = threadIdx.x; j < m; j += kHllBlock) regs[((uint64_t)b << p) + j] = R[j];
+        __syncthreads();   // R is cleared for the next bin
+    }
+}
+
+template <int W>
+hipError_t hll_w(const uint64_t* packed, uint64_t n_bytes, const uint64_t* desc, const uint64_t* bin_off,
+                 uint32_t n_bins, uint32_t k, uint32_t canonical, uint32_t p, uint32_t* regs, hipStream_t s) {
+    const size_t lds = (size_t)4 << p;
+    if (lds > 64 * 1024 &&
+        hipFuncSetAttribute((const void*)k_hll<W>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return hipErrorInvalidValue;
+    const uint32_t grid = n_bins < 4096 ? (n_bins ? n_bins : 1) : 4096;
+    hipLaunchKernelGGL(k_hll<W>, dim3(grid), dim3(kHllBlock), lds, s, packed, n_bytes, desc, bin_off, n_bins, k,
+                       canonical, p, regs);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_hll(const uint64_t* packed, uint64_t n_bytes, const uint64_t* desc, const uint64_t* bin_off,
+                      uint32_t n_bins, uint32_t k, uint32_t canonical, uint32_t p, uint32_t* regs, hipStream_t s) {
+    switch ((k + 31) / 32) {
+        case 1: return hll_w<1>(packed, n_bytes, desc, bin_off, n_bins, k, canonical, p, regs, s);
+        case 2: return hll_w<2>(packed, n_bytes, desc, bin_off, n_bins, k, canonical, p, regs, s);
+        case 3: return hll_w<3>(packed, n_bytes, desc, bin_off, n_bins, k, canonical, p, regs, s);
+        case 4: return hll_w<4>(packed, n_bytes, desc, bin_off, n_bins, k, canonical, p, regs, s);
+        case 5: return hll_w<5>(packed, n_bytes, desc, bin_off, n_bins, k, canonical, p, regs, s);
+        case 6: return hll_w<6>(packed, n_bytes, desc, bin_off, n_bins, k, canonical, p, regs, s);
+        case 7: return hll_w<7>(packed, n_bytes, desc, bin_off, n_bins, k, canonical, p, regs, s);
+        case 8: return hll_w<8>(packed, n_bytes, desc, bin_off, n_bins, k, canonical, p, regs, s);
+        case 9: return hll_w<9>(packed, n_bytes, desc, bin_off, n_bins, k, canonical, p, regs, s);
+        case 10: return hll_w<10>(packed, n_bytes, desc, bin_off, n_bins, k, canonical, p, regs, s);
+        case 11: return hll_w<11>(packed, n_bytes, desc, bin_off, n_bins, k, canonical, p, regs, s);
+        case 12: return hll_w<12>(packed, n_bytes, desc, bin_off, n_bins, k, canonical, p, regs, s);
+        case 13: return hll_w<13>(packed, n_bytes, desc, bin_off, n_bins, k, canonical, p, regs, s);
+        case 14: return hll_w<14>(packed, n_bytes, desc, bin_off, n_bins, k, canonical, p, regs, s);
+        case 15: return hll_w<15>(packed, n_bytes, desc, bin_off, n_bins, k, canonical, p, regs, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace gerbil

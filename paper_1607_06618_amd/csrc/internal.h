@@ -45,6 +45,9 @@ struct BinArgs {
 hipError_t launch_bin(const BinArgs& a, uint32_t max_grid, uint32_t cus, hipStream_t s);
 // bins[i] = the bin gerbil_bin gives key i (uses a.k, a.m, a.order, a.rank_table, a.bin_map, a.n_bins)
 hipError_t launch_key_bins(const uint64_t* keys, uint64_t n, const BinArgs& a, uint32_t* bins, hipStream_t s);
+// HyperLogLog registers [n_bins << p] of every bin's canonical (or, canonical = 0, as read) k-mers
+hipError_t launch_hll(const uint64_t* packed, uint64_t n_bytes, const uint64_t* desc, const uint64_t* bin_off,
+                      uint32_t n_bins, uint32_t k, uint32_t canonical, uint32_t p, uint32_t* regs, hipStream_t s);
 // The tile kernel hands out list slots to each workgroup in chunks of at
 // least kListChunk and fills them without gaps; only the unused end of each
 // workgroup's last chunk (under kListChunk slots) is a hole. At most

@@ -159,6 +159,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gerbil_parse_workspace.argtypes = [u64, u64, P(u64)]
     lib.gerbil_order_table_workspace.argtypes = [u32, u32, P(u64)]
     lib.gerbil_key_bins.argtypes = [vp, u64, P(gerbil_params), vp, vp]
+    lib.gerbil_hll_bins.argtypes = [P(gerbil_bins), P(gerbil_params), u32, vp, vp]
     lib.gerbil_order_table.argtypes = [u32, u32, u64, f32, u32, P(gerbil_encoded), vp, u64, vp, vp]
     lib.gerbil_parse.argtypes = [vp, u64, u32, vp, u64, u64, vp, u64, vp, u64, vp, vp]
     for name in ("gerbil_encode_workspace", "gerbil_encode", "gerbil_bin_workspace", "gerbil_bin",
@@ -166,7 +167,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                  "gerbil_graph_capture", "gerbil_graph_launch", "gerbil_graph_info", "gerbil_graph_destroy",
                  "gerbil_autotune_workspace", "gerbil_autotune", "gerbil_autotune_reset",
                  "gerbil_records_workspace", "gerbil_records", "gerbil_parse_workspace", "gerbil_parse",
-                 "gerbil_order_table_workspace", "gerbil_order_table", "gerbil_key_bins"):
+                 "gerbil_order_table_workspace", "gerbil_order_table", "gerbil_key_bins",
+                 "gerbil_hll_bins"):
         getattr(lib, name).restype = ctypes.c_int32
     _lib = lib
     return lib
@@ -318,6 +320,18 @@ def records(keys_d, counts_d, n: int, k: int, stream=None):
 
 def gerbil_key_bins(keys_ptr: int, n: int, params: gerbil_params, bins_ptr: int, stream: int = 0) -> int:
     return load().gerbil_key_bins(keys_ptr or None, n, ctypes.byref(params), bins_ptr or None, stream)
+
+
+def gerbil_hll_bins(bins: gerbil_bins, params: gerbil_params, log2_regs: int, regs_ptr: int, stream: int = 0) -> int:
+    return load().gerbil_hll_bins(ctypes.byref(bins), ctypes.byref(params), log2_regs, regs_ptr or None, stream)
+
+
+def hll_registers(job, log2_regs: int = 12, stream=None):
+    """HyperLogLog registers [n_bins, 2^log2_regs] of a binned job (device int32 tensor)."""
+    import torch
+    regs = torch.empty((job.bins.n_bins, 1 << log2_regs), dtype=torch.int32, device=job.ascii_d.device)
+    check("gerbil_hll_bins", gerbil_hll_bins(job.bins, job.p, log2_regs, regs.data_ptr(), _stream_handle(stream)))
+    return regs
 
 
 def key_bins(keys_d, n: int, params: gerbil_params, stream=None):
