@@ -185,3 +185,17 @@ def test_order_table_validation():
                                                 bin_map_ptr=fake))
     assert g.gerbil_bin_workspace(e, g.make_params(32, 7, 64, 2, order=g.GERBIL_ORDER_TABLE,
                                                    rank_table_ptr=fake)) > 0
+
+
+def test_key_bins_and_hll_validation():
+    fake = 4096
+    p = g.make_params(65, 9, 64, 1)
+    assert g.gerbil_key_bins(0, 10, p, fake) == g.GERBIL_EINVAL       # keys missing
+    assert g.gerbil_key_bins(fake, 10, p, 0) == g.GERBIL_EINVAL       # output missing
+    assert g.gerbil_key_bins(fake, 10, g.make_params(65, 0, 64, 1), fake) == g.GERBIL_EINVAL
+    bins = g.gerbil_bins(k=65, n_bins=64, packed=fake, desc=fake, bin_off=fake)
+    assert g.gerbil_hll_bins(bins, p, 3, fake) == g.GERBIL_EINVAL      # too few registers
+    assert g.gerbil_hll_bins(bins, p, 16, fake) == g.GERBIL_EINVAL     # too many
+    assert g.gerbil_hll_bins(bins, p, 12, 0) == g.GERBIL_EINVAL
+    assert g.gerbil_hll_bins(bins, g.make_params(33, 9, 64, 1), 12, fake) == g.GERBIL_EINVAL   # k differs
+    assert g.gerbil_hll_bins(g.gerbil_bins(k=65, n_bins=64), p, 12, fake) == g.GERBIL_EINVAL  # no bins
