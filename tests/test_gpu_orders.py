@@ -182,3 +182,55 @@ def test_hll_sketches_estimate_distinct_keys_per_bin(canonical):
     assert regs.max() <= 64 - 12 + 1 and regs.min() >= 0
     rel = np.abs(hll_estimate(regs) - distinct) / distinct
     assert rel.max() < 0.08, rel   # standard error 1.04 / sqrt(4096) = 1.6%
+
+
+_M64 = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+def _fmix64(z):
+    z = z ^ (z >> np.uint64(33))
+    z = z * np.uint64(0xFF51AFD7ED558CCD)
+    z = z ^ (z >> np.uint64(33))
+    z = z * np.uint64(0xC4CEB9FE1A85EC53)
+    return z ^ (z >> np.uint64(33))
+
+
+def _key_hash(keys, seed):
+    """The library's key hash (words XOR-folded at rotations 23 i mod 64, then
+    the MurmurHash3 finaliser), vectorised over rows of keys."""
+    h = np.uint64(seed) ^ keys[:, 0]
+    for i in range(1, keys.shape[1]):
+        r = np.uint64((23 * i) & 63)
+        h = h ^ ((keys[:, i] << r) | (keys[:, i] >> ((np.uint64(64) - r) & np.uint64(63))))
+    return _fmix64(h)
+
+
+def _bit_length(x):
+    n = np.zeros(x.shape, dtype=np.int64)
+    y = x.copy()
+    for s in (32, 16, 8, 4, 2, 1):
+        big = y >= (np.uint64(1) << np.uint64(s))
+        n[big] += s
+        y[big] >>= np.uint64(s)
+    return n + (y > 0)
+
+
+@pytest.mark.parametrize("k", [31, 65, 200])
+def test_hll_registers_equal_those_of_the_distinct_keys(k):
+    """A register keeps a maximum, so the sketch of a bin's occurrences equals
+    the sketch of its distinct keys: the registers from the super-mers must
+    match, exactly, registers built on the host from the emitted keys."""
+    a, o = sample_reads(3 * k, n=300, lo=k, hi=k + 500)
+    nb, p = 16, 10
+    job = make_job(a, o, k, m=9, n_bins=nb, threshold=1, mode=g.GERBIL_BATCHED)
+    job.run()
+    res = job.result()
+    n = res.counts.size
+    bins = g.key_bins(job.keys_d, n, job.p).cpu().numpy().astype(np.int64)
+    regs = g.hll_registers(job, p).cpu().numpy()
+    h = _key_hash(res.keys.astype(np.uint64), 0x5BD1E9955BD1E995)
+    idx = (h >> np.uint64(64 - p)).astype(np.int64)
+    rho = 64 - _bit_length((h << np.uint64(p)) | np.uint64(1 << (p - 1))) + 1
+    want = np.zeros((nb, 1 << p), dtype=np.int64)
+    np.maximum.at(want, (bins, idx), rho)
+    assert np.array_equal(regs.astype(np.int64), want)
