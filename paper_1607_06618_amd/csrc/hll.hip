@@ -1,9 +1,10 @@
 // HyperLogLog sketches of the distinct k-mers of every bin, from the k-mer
 // occurrences of its super-mers: the alternative the table-size estimate
 // of Sec. 3.4.1 is compared with. One workgroup per bin keeps the bin's 2^p
-// registers in LDS; each thread walks one super-mer, hashes every canonical
-// key and raises register (top p bits of the hash) to the rank of the first
-// set bit of the remaining bits; the registers are written out once.
+// registers in LDS; each thread walks one super-mer, rolling its window one
+// base at a time, hashes every canonical key and raises register (top p bits
+// of the hash) to the rank of the first set bit of the remaining bits; the
+// registers are written out once.
 #include "../../include/gerbil.h"
 #include "common.h"
 #include "internal.h"
@@ -13,6 +14,26 @@ namespace {
 
 constexpr uint32_t kHllBlock = 256;
 constexpr uint64_t kHllSeed = 0x5bd1e9955bd1e995ull;   // not the table seed: an independent hash
+
+// Advance a window by one base b: fw drops its first base and appends b; rc
+// drops its last base and takes the complement of b in front. The last word
+// holds r bases, right-aligned.
+template <int W>
+__device__ __forceinline__ void roll_kmer(uint64_t (&fw)[W], uint64_t (&rc)[W], uint32_t r, uint64_t b) {
+#pragma unroll
+    for (int i = 0; i + 1 < W; i++) {
+        const uint32_t top = i + 2 < W ? 62u : 2u * r - 2u;   // the first base of word i + 1
+        fw[i] = (fw[i] << 2) | ((fw[i + 1] >> top) & 3ull);
+    }
+    const uint64_t lmask = r == 32 ? ~0ull : ((1ull << (2 * r)) - 1ull);
+    fw[W - 1] = ((fw[W - 1] << 2) | b) & lmask;
+#pragma unroll
+    for (int i = W - 1; i >= 1; i--) {
+        const uint32_t top = i == W - 1 ? 2u * r - 2u : 62u;
+        rc[i] = (rc[i] >> 2) | ((rc[i - 1] & 3ull) << top);
+    }
+    rc[0] = (rc[0] >> 2) | ((3ull - b) << (W == 1 ? 2u * r - 2u : 62u));
+}
 
 template <int W>
 __global__ void __launch_bounds__(kHllBlock) k_hll(const uint64_t* __restrict__ packed, uint64_t n_bytes,
@@ -30,9 +51,15 @@ __global__ void __launch_bounds__(kHllBlock) k_hll(const uint64_t* __restrict__ 
             const int64_t start = (int64_t)(dd >> 24);
             const uint32_t nk = (uint32_t)(dd & 0xFFFFFFu);
             if (nk == 0 || start < 0 || (uint64_t)start + nk - 1 + k > n_bytes) continue;   // never read out of range
+            const uint32_t r = k - 32u * (W - 1);
+            uint64_t fw[W], rc[W];
+            extract_kmer<W>(packed, start, k, fw, rc);
             for (uint32_t t = 0; t < nk; t++) {
-                uint64_t fw[W], rc[W], key[W];
-                extract_kmer<W>(packed, start + t, k, fw, rc);
+                if (t) {   // the next window: one more base from the packed stream
+                    const uint64_t pos = (uint64_t)start + t + k - 1;
+                    roll_kmer<W>(fw, rc, r, (packed[pos >> 5] >> (62 - 2 * (pos & 31))) & 3ull);
+                }
+                uint64_t key[W];
                 canonical_of<W>(fw, rc, key, canonical);
                 const uint64_t h = key_hash<W>(key, kHllSeed);
                 const uint32_t idx = (uint32_t)(h >> (64 - p));
