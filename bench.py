@@ -49,6 +49,8 @@ def parse_args(argv=None):
     ap.add_argument("--serving", type=int, default=0, help="also serve this many jobs of the Poisson job stream")
     ap.add_argument("--serving-scale", type=float, default=1.0, help="genome-size scale of the served jobs")
     ap.add_argument("--serving-inflight", type=int, default=4)
+    ap.add_argument("--size-sample", type=int, default=0,
+                    help="LDS run sizing: every n-th segment is counted (0 = library default, 1 = exact)")
     ap.add_argument("--k", type=int, default=0, help="override the workload's k (keys above 256 bases use HBM tables)")
     ap.add_argument("--non-canonical", action="store_true",
                     help="count k-mers as read, without reverse-complement normalisation (-d)")
@@ -225,7 +227,7 @@ def main(argv=None):
         if w.k > 256 and args.table == "lds":
             table = g.GERBIL_TABLE_HBM   # LDS tables hold keys of up to 256 bases
         p = g.make_params(w.k, w.m, w.n_bins, w.threshold, mode=mode, pool=args.pool, load_factor=args.load, table=table,
-                          canonical=not args.non_canonical,
+                          canonical=not args.non_canonical, size_sample=args.size_sample,
                           bin_map_ptr=bin_map_d.data_ptr() if bin_map_d is not None else 0,
                           timing_events=ctypes.addressof(ev))
         clocks_d = None
@@ -326,7 +328,7 @@ def main(argv=None):
              ("batched", "hbm"): "k_count_persistent", ("plain", "hbm"): "k_count_bin+k_compact"}[(head, head_table)]
     traffic = None
     default_schedule = (not args.tune and args.load == 0.0 and args.pool == 0 and args.scale == 1.0
-                        and not args.non_canonical)
+                        and not args.non_canonical and args.size_sample == 0)
     if default_schedule and "+" not in kname:
         traffic = measured_traffic(kname, w.name)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
