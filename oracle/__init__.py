@@ -34,6 +34,10 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+class _Keys(ctypes.Structure):
+    _fields_ = [("keys", ctypes.POINTER(ctypes.c_uint64)), ("n", ctypes.c_uint64), ("cap", ctypes.c_uint64)]
+
+
 class _Result(ctypes.Structure):
     _fields_ = [("n_valid", ctypes.c_uint64), ("n_valid_shard", ctypes.c_uint64),
                 ("n_distinct", ctypes.c_uint64), ("n_pairs", ctypes.c_uint64),
@@ -63,6 +67,14 @@ def _load():
         lib.oracle_supermers.restype = i32
         lib.oracle_shard_of.argtypes = [vp, u32, u64]
         lib.oracle_shard_of.restype = u64
+        lib.oracle_shard_of_many.argtypes = [vp, u64, u32, u64, vp]
+        lib.oracle_shard_of_many.restype = None
+        lib.oracle_collect.argtypes = [vp, vp, u64, u64, u32, u32, u64, u64, u64, vp, vp]
+        lib.oracle_collect.restype = i32
+        lib.oracle_count_multiset.argtypes = [vp, u64, u32, u32, ctypes.POINTER(_Result)]
+        lib.oracle_count_multiset.restype = i32
+        lib.oracle_keys_free.argtypes = [vp]
+        lib.oracle_keys_free.restype = None
         lib.oracle_record.argtypes = [ctypes.c_char_p, u32, u32, vp]
         lib.oracle_record.restype = u32
         _lib = lib
@@ -110,15 +122,116 @@ def count(ascii: np.ndarray, offsets: np.ndarray, k: int, threshold: int = 1, ca
     if rc != 0:
         raise RuntimeError(f"oracle_count failed with status {rc}")
     try:
-        W = words(k)
-        n = r.n_pairs
-        keys = np.ctypeslib.as_array(r.keys, shape=(max(n, 1) * W,))[: n * W].reshape(n, W).copy()
-        counts = np.ctypeslib.as_array(r.counts, shape=(max(n, 1),))[:n].copy()
-        hist = np.ctypeslib.as_array(r.hist, shape=(r.hist_len,)).copy() if r.hist_len else \
-            np.zeros(1, dtype=np.uint64)
-        return Counted(k, int(r.n_valid), int(r.n_valid_shard), int(r.n_distinct), keys, counts, hist)
+        return _counted(k, r)
     finally:
         lib.oracle_free(ctypes.byref(r))
+
+
+def _counted(k: int, r: "_Result") -> Counted:
+    W = words(k)
+    n = r.n_pairs
+    keys = np.ctypeslib.as_array(r.keys, shape=(max(n, 1) * W,))[: n * W].reshape(n, W).copy()
+    counts = np.ctypeslib.as_array(r.counts, shape=(max(n, 1),))[:n].copy()
+    hist = np.ctypeslib.as_array(r.hist, shape=(r.hist_len,)).copy() if r.hist_len else \
+        np.zeros(1, dtype=np.uint64)
+    return Counted(k, int(r.n_valid), int(r.n_valid_shard), int(r.n_distinct), keys, counts, hist)
+
+
+def count_multiset(keys: np.ndarray, k: int, threshold: int = 1) -> Counted:
+    """Steps 6-9 of the definition over a multiset of packed keys ([n, W]
+    uint64, sorted in place): see ``oracle_count_multiset`` in the C file."""
+    lib = _load()
+    W = words(k)
+    ks = keys.reshape(-1, W)
+    assert ks.dtype == np.uint64 and ks.flags["C_CONTIGUOUS"]
+    r = _Result()
+    rc = lib.oracle_count_multiset(ks.ctypes.data, ks.shape[0], W, threshold, ctypes.byref(r))
+    if rc != 0:
+        lib.oracle_free(ctypes.byref(r))
+        raise RuntimeError(f"oracle_count_multiset failed with status {rc}")
+    try:
+        return _counted(k, r)
+    finally:
+        lib.oracle_free(ctypes.byref(r))
+
+
+def count_sharded(ascii: np.ndarray, offsets: np.ndarray, k: int, threshold: int, shard_mod: int,
+                  on_shard, canonical: bool = True, group: int = 0, threads: int = 8, sort_workers: int = 2) -> int:
+    """The result of ``count`` split into ``shard_mod`` shards by
+    ``oracle_shard_of``, for read sets whose keys do not fit in memory at once.
+
+    Shards are taken ``group`` at a time (0: all at once). For each group the
+    reads are cut into ``threads`` ranges whose keys are collected
+    concurrently (steps 1-5, ``oracle_collect``); then each shard's keys are
+    joined and counted (steps 6-9, ``oracle_count_multiset``), and
+    ``on_shard(s, Counted)`` is called once per shard, in shard order within a
+    group. Every key lands in exactly one shard, so the shards' pairs are the
+    pairs of ``count`` and their histograms add up to its histogram. Returns the
+    number of valid windows of the input. Memory: the keys of one group, plus
+    about two shards per sort worker."""
+    import concurrent.futures as cf
+    lib = _load()
+    W = words(k)
+    a, o = _c(ascii, np.uint8), _c(offsets, np.uint64)
+    n_reads = o.size - 1
+    group = shard_mod if group <= 0 else min(group, shard_mod)
+    cuts = np.linspace(0, n_reads, max(1, threads) + 1).astype(np.int64)
+    L = np.diff(o.astype(np.int64))
+    win = np.maximum(L - k + 1, 0)
+    win_cum = np.concatenate([[0], np.cumsum(win)])
+    n_valid_total = None
+    for s_lo in range(0, shard_mod, group):
+        s_hi = min(shard_mod, s_lo + group)
+        G = s_hi - s_lo
+        outs = []
+        for t in range(len(cuts) - 1):
+            arr = (_Keys * G)()
+            expect = int(win_cum[cuts[t + 1]] - win_cum[cuts[t]]) / max(1, shard_mod)
+            for i in range(G):
+                arr[i].cap = int(expect * 1.02) + 4096
+            outs.append(arr)
+        nv = [np.zeros(1, dtype=np.uint64) for _ in outs]
+
+        def collect(t):
+            return lib.oracle_collect(a.ctypes.data, o.ctypes.data, int(cuts[t]), int(cuts[t + 1]), k,
+                                      int(canonical), shard_mod, s_lo, s_hi, ctypes.addressof(outs[t]),
+                                      nv[t].ctypes.data)
+
+        try:
+            with cf.ThreadPoolExecutor(max_workers=len(outs)) as ex:
+                rcs = list(ex.map(collect, range(len(outs))))
+            if any(rc != 0 for rc in rcs):
+                raise RuntimeError(f"oracle_collect failed with status {rcs}")
+            n_valid = int(sum(int(x[0]) for x in nv))
+            if n_valid_total is None:
+                n_valid_total = n_valid
+            assert n_valid == n_valid_total
+
+            def count_shard(i):
+                n = sum(int(outs[t][i].n) for t in range(len(outs)))
+                joined = np.empty((max(n, 1), W), dtype=np.uint64)
+                pos = 0
+                for t in range(len(outs)):
+                    part = outs[t][i]
+                    if part.n:
+                        src = np.ctypeslib.as_array(part.keys, shape=(int(part.n) * W,))
+                        joined.reshape(-1)[pos * W: (pos + int(part.n)) * W] = src
+                        pos += int(part.n)
+                    lib.oracle_keys_free(ctypes.byref(part))
+                res = count_multiset(joined[:n], k, threshold)
+                del joined
+                res.n_valid = n_valid
+                return res
+
+            with cf.ThreadPoolExecutor(max_workers=max(1, sort_workers)) as ex:
+                futs = [ex.submit(count_shard, i) for i in range(G)]
+                for i, f in enumerate(futs):
+                    on_shard(s_lo + i, f.result())
+        finally:
+            for arr in outs:
+                for i in range(G):
+                    lib.oracle_keys_free(ctypes.byref(arr[i]))
+    return int(n_valid_total or 0)
 
 
 def count_keys(ascii: np.ndarray, offsets: np.ndarray, k: int, query: np.ndarray) -> np.ndarray:
@@ -211,12 +324,21 @@ def supermers(ascii: np.ndarray, offsets: np.ndarray, k: int, m: int, n_bins: in
 
 def shard_of(keys: np.ndarray, k: int, shard_mod: int) -> np.ndarray:
     """Shard id of each key row (the oracle's memory-bounding partition)."""
+    import concurrent.futures as cf
     lib = _load()
     W = words(k)
     ks = _c(keys, np.uint64).reshape(-1, W)
-    out = np.empty(ks.shape[0], dtype=np.uint64)
-    for i in range(ks.shape[0]):
-        out[i] = lib.oracle_shard_of(ks[i].ctypes.data, W, shard_mod)
+    n = ks.shape[0]
+    out = np.empty(n, dtype=np.uint64)
+    cuts = np.linspace(0, n, 17).astype(np.int64) if n > (1 << 20) else np.array([0, n])
+
+    def part(i):
+        lo, hi = int(cuts[i]), int(cuts[i + 1])
+        if hi > lo:
+            lib.oracle_shard_of_many(ks[lo:hi].ctypes.data, hi - lo, W, shard_mod, out[lo:hi].ctypes.data)
+
+    with cf.ThreadPoolExecutor(max_workers=len(cuts) - 1) as ex:
+        list(ex.map(part, range(len(cuts) - 1)))
     return out
 
 

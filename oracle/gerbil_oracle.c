@@ -148,32 +148,61 @@ void oracle_free(oracle_result* r) {
 }
 
 /*
- * Count canonical k-mers (canonical != 0) or plain k-mers (canonical == 0,
- * the paper's `-d`). Keeps only keys with oracle_shard_of(key) == shard_id
- * when shard_mod > 1. Output pairs are those with count >= threshold; the
- * histogram covers every distinct key of the shard.
+ * A growable array of keys of W words each. Used to hand the keys of one
+ * shard from the collecting step to the counting step.
  */
-int oracle_count(const uint8_t* ascii, const uint64_t* offsets, uint64_t n_reads, uint32_t k,
-                 uint32_t threshold, uint32_t canonical, uint64_t shard_mod, uint64_t shard_id,
-                 oracle_result* out) {
-    memset(out, 0, sizeof(*out));
-    if (k < 1 || k > 1024) return ORACLE_EINVAL;
+typedef struct {
+    uint64_t* keys;   /* [cap * W] */
+    uint64_t n;       /* keys held */
+    uint64_t cap;     /* keys allocated; a caller may preset it before the first push */
+} oracle_keys;
+
+void oracle_keys_free(oracle_keys* a) {
+    free(a->keys);
+    a->keys = NULL;
+    a->n = a->cap = 0;
+}
+
+static int keys_push(oracle_keys* a, const uint64_t* key, uint32_t W) {
+    if (!a->keys || a->n == a->cap) {
+        uint64_t cap = a->keys ? a->cap + a->cap / 4 + 1024 : (a->cap ? a->cap : 1024);
+        uint64_t* grown = (uint64_t*)realloc(a->keys, cap * 8 * W);
+        if (!grown) return ORACLE_ENOMEM;
+        a->keys = grown;
+        a->cap = cap;
+    }
+    memcpy(a->keys + a->n * W, key, 8 * W);
+    a->n++;
+    return ORACLE_OK;
+}
+
+/*
+ * Steps 1-5 of the definition over reads [r0, r1): every window of every read
+ * (windows never span two reads); windows holding a byte other than A, C, G, T
+ * (either case) are skipped (Sec. 2.4.1); the key is the lexicographically
+ * smaller of the window and its reverse complement (Sec. 2.4.2), or the window
+ * itself when canonical == 0 (App. A `-d`); it is packed into W words.
+ * A key whose shard s = oracle_shard_of(key, W, shard_mod) lies in
+ * [s_lo, s_hi) is appended to outs[s - s_lo]. *n_valid receives the number of
+ * valid windows of the range (all shards).
+ */
+int oracle_collect(const uint8_t* ascii, const uint64_t* offsets, uint64_t r0, uint64_t r1, uint32_t k,
+                   uint32_t canonical, uint64_t shard_mod, uint64_t s_lo, uint64_t s_hi,
+                   oracle_keys* outs /* [s_hi - s_lo] */, uint64_t* n_valid) {
+    *n_valid = 0;
+    if (k < 1 || k > 1024 || s_hi <= s_lo) return ORACLE_EINVAL;
     uint32_t W = words_for(k);
     char* s = (char*)malloc(k);
     char* t = (char*)malloc(k);
     uint64_t* key = (uint64_t*)malloc(8 * W);
-    uint64_t cap = 1 << 16, n = 0;
-    uint64_t* all = (uint64_t*)malloc(cap * 8 * W);
-    if (!s || !t || !key || !all) return ORACLE_ENOMEM;
-
-    /* Steps 1-5: every window of every read; skip windows with an invalid
-     * byte; canonical = lexicographically smaller of x and rc(x). */
-    for (uint64_t r = 0; r < n_reads; r++) {
+    if (!s || !t || !key) { free(s); free(t); free(key); return ORACLE_ENOMEM; }
+    int status = ORACLE_OK;
+    for (uint64_t r = r0; r < r1 && status == ORACLE_OK; r++) {
         const uint8_t* R = ascii + offsets[r];
         uint64_t L = offsets[r + 1] - offsets[r];
         for (uint64_t i = 0; i + k <= L; i++) {
             if (!window_ok(R + i, k)) continue;
-            out->n_valid++;
+            (*n_valid)++;
             for (uint32_t j = 0; j < k; j++) s[j] = upper(R[i + j]);
             const char* c = s;
             if (canonical) {
@@ -181,17 +210,24 @@ int oracle_count(const uint8_t* ascii, const uint64_t* offsets, uint64_t n_reads
                 if (memcmp(t, s, k) < 0) c = t;
             }
             pack(c, k, key);
-            if (shard_mod > 1 && oracle_shard_of(key, W, shard_mod) != shard_id) continue;
-            if (n == cap) {
-                cap *= 2;
-                uint64_t* grown = (uint64_t*)realloc(all, cap * 8 * W);
-                if (!grown) { free(all); free(s); free(t); free(key); return ORACLE_ENOMEM; }
-                all = grown;
-            }
-            memcpy(all + n * W, key, 8 * W);
-            n++;
+            uint64_t sh = oracle_shard_of(key, W, shard_mod);
+            if (sh < s_lo || sh >= s_hi) continue;
+            status = keys_push(&outs[sh - s_lo], key, W);
+            if (status != ORACLE_OK) break;
         }
     }
+    free(s); free(t); free(key);
+    return status;
+}
+
+/*
+ * Steps 6-9 of the definition over a multiset of n keys (sorted in place):
+ * sort, run-length, the pairs with count >= threshold (App. A `-l`) in
+ * ascending key order, and the histogram of the counts of every distinct key.
+ */
+int oracle_count_multiset(uint64_t* all, uint64_t n, uint32_t W, uint32_t threshold, oracle_result* out) {
+    memset(out, 0, sizeof(*out));
+    if (W < 1) return ORACLE_EINVAL;
     out->n_valid_shard = n;
 
     /* Step 6: sort the multiset, then run-length it. */
@@ -205,7 +241,7 @@ int oracle_count(const uint8_t* ascii, const uint64_t* offsets, uint64_t n_reads
         i = j;
     }
     /* Step 9: counters are 32-bit. */
-    if (max_count >= 0xFFFFFFFFull) { free(all); free(s); free(t); free(key); return ORACLE_ECOUNT; }
+    if (max_count >= 0xFFFFFFFFull) return ORACLE_ECOUNT;
 
     /* Steps 7-8: pairs with count >= threshold; histogram of all counts. */
     out->hist_len = max_count + 1;
@@ -220,6 +256,7 @@ int oracle_count(const uint8_t* ascii, const uint64_t* offsets, uint64_t n_reads
     }
     out->keys = (uint64_t*)malloc((n_pairs ? n_pairs : 1) * 8 * W);
     out->counts = (uint32_t*)malloc((n_pairs ? n_pairs : 1) * 4);
+    if (!out->hist || !out->keys || !out->counts) { oracle_free(out); return ORACLE_ENOMEM; }
     uint64_t o = 0;
     for (uint64_t i = 0; i < n;) {
         uint64_t j = i + 1;
@@ -234,8 +271,36 @@ int oracle_count(const uint8_t* ascii, const uint64_t* offsets, uint64_t n_reads
     out->n_distinct = n_distinct;
     out->n_pairs = n_pairs;
     out->max_count = max_count;
-    free(all); free(s); free(t); free(key);
     return ORACLE_OK;
+}
+
+/*
+ * Count canonical k-mers (canonical != 0) or plain k-mers (canonical == 0,
+ * the paper's `-d`): steps 1-5 over every read, then steps 6-9. Keeps only
+ * keys with oracle_shard_of(key) == shard_id when shard_mod > 1. Output pairs
+ * are those with count >= threshold; the histogram covers every distinct key
+ * of the shard.
+ */
+int oracle_count(const uint8_t* ascii, const uint64_t* offsets, uint64_t n_reads, uint32_t k,
+                 uint32_t threshold, uint32_t canonical, uint64_t shard_mod, uint64_t shard_id,
+                 oracle_result* out) {
+    memset(out, 0, sizeof(*out));
+    if (k < 1 || k > 1024) return ORACLE_EINVAL;
+    if (shard_mod <= 1) shard_id = 0;
+    oracle_keys keys = {NULL, 0, 0};
+    uint64_t n_valid = 0;
+    int status = oracle_collect(ascii, offsets, 0, n_reads, k, canonical, shard_mod, shard_id, shard_id + 1, &keys,
+                                &n_valid);
+    if (status == ORACLE_OK) status = oracle_count_multiset(keys.keys, keys.n, words_for(k), threshold, out);
+    out->n_valid = n_valid;
+    oracle_keys_free(&keys);
+    return status;
+}
+
+/* Shard of each of n keys (oracle_shard_of), for splitting a large result the
+ * way the oracle splits its work. */
+void oracle_shard_of_many(const uint64_t* keys, uint64_t n, uint32_t W, uint64_t shard_mod, uint64_t* out) {
+    for (uint64_t i = 0; i < n; i++) out[i] = oracle_shard_of(keys + i * W, W, shard_mod);
 }
 
 /*

@@ -61,3 +61,62 @@ def random_reads(rng, n, min_len, max_len, n_rate=0.02, lower_rate=0.02, junk="N
         s = np.where(bad, rng.choice(list(junk), L), s)
         reads.append("".join(s.tolist()))
     return reads
+
+
+def shard_digests_device(keys_d, counts_d, n, W, k, shard_mod, threads=16):
+    """Per-shard (pair count, SHA-256) of emitted pairs, in the layout the
+    full-size golden files use: pairs of shard s (``oracle.shard_of``) in
+    ascending key order. Sorting runs on the device (stable sorts, last word
+    first, then by shard); shard ids and digests are computed on the host."""
+    import concurrent.futures as cf
+    import os
+    import sys
+
+    import torch
+
+    import oracle
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+    import fullsize
+
+    dev = keys_d.device
+    rows = keys_d[: n * W].view(n, W)
+    shard = oracle.shard_of(rows.cpu().numpy().view(np.uint64), k, shard_mod)
+    shard_d = torch.from_numpy(shard.view(np.int64)).to(dev)
+    sign = torch.iinfo(torch.int64).min   # flips the sign bit: signed order = unsigned order
+    perm = torch.arange(n, device=dev)
+    for w in reversed(range(W)):
+        _, idx = torch.sort(rows[perm, w] ^ sign, stable=True)
+        perm = perm[idx]
+    _, idx = torch.sort(shard_d[perm], stable=True)
+    perm = perm[idx]
+    keys_s = rows[perm].cpu().numpy().view(np.uint64)
+    counts_s = counts_d[:n][perm].cpu().numpy().view(np.uint32)
+    per = np.bincount(shard.astype(np.int64), minlength=shard_mod)
+    bounds = np.concatenate([[0], np.cumsum(per)])
+
+    def one(s):
+        lo, hi = int(bounds[s]), int(bounds[s + 1])
+        return int(hi - lo), fullsize.pairs_digest(keys_s[lo:hi], counts_s[lo:hi])
+
+    with cf.ThreadPoolExecutor(threads) as ex:
+        return list(ex.map(one, range(shard_mod)))
+
+
+def shard_digests_host(keys, counts, k, shard_mod):
+    """The same digests for pairs already on the host (any order)."""
+    import os
+    import sys
+
+    import oracle
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+    import fullsize
+
+    keys = np.ascontiguousarray(keys, dtype=np.uint64).reshape(-1, (k + 31) // 32)
+    shard = oracle.shard_of(keys, k, shard_mod) if keys.shape[0] else np.zeros(0, np.uint64)
+    order = np.lexsort(tuple(keys.T[::-1]) + (shard,)) if keys.shape[0] else np.zeros(0, np.int64)
+    keys, counts, shard = keys[order], np.asarray(counts, dtype=np.uint32)[order], shard[order]
+    out = []
+    for s in range(shard_mod):
+        sel = shard == s
+        out.append((int(sel.sum()), fullsize.pairs_digest(keys[sel], counts[sel])))
+    return out

@@ -65,3 +65,52 @@ def test_admission_respects_the_budget_and_output_retry():
         ref = oracle.count(a, o, w.k, threshold=w.threshold)
         k_, c_ = r.sorted()
         assert np.array_equal(k_, ref.keys) and np.array_equal(c_, ref.counts)
+
+
+# The smallest seeded job of each k among the first 200 jobs of the stream,
+# at their full (unscaled) sizes; their oracle results are stored as digests.
+FULL_JOBS = (199, 129, 135)
+
+
+def _fold(hist: np.ndarray, length: int) -> np.ndarray:
+    h = np.zeros(length, dtype=np.uint64)
+    h[: length - 1] = hist[: length - 1]
+    h[length - 1] = hist[length - 1:].sum()
+    return h
+
+
+@pytest.mark.slow
+def test_full_size_jobs_alone_and_mixed():
+    import os
+    import sys
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+    import fullsize
+    from gpu_util import shard_digests_host
+
+    reqs, golds = [], []
+    for j in FULL_JOBS:
+        gold = fullsize.read(f"job{j}")
+        w = synth.serving_job(j, scale=1.0)
+        a, o = w.generate()
+        assert fullsize.input_fingerprint(a, o) == gold.fields["input"], "the generated reads changed"
+        golds.append((w, gold))
+        reqs.append(serve.make_request(j, a, o, w.k, w.m, w.n_bins, w.threshold, arrival=0.0))
+    assert sorted(w.k for w, _ in golds) == [32, 55, 99]
+    alone = []
+    for r in reqs:
+        alone.extend(serve.CountingServer(budget_bytes=64 << 30, max_inflight=1).serve([r], realtime=False))
+    mixed = serve.CountingServer(budget_bytes=64 << 30, max_inflight=4).serve(reqs, realtime=False)
+    alone = sorted(alone, key=lambda r: r.job_id)
+    by_id = dict(zip(FULL_JOBS, golds))
+    assert [r.job_id for r in mixed] == [r.job_id for r in alone] == sorted(FULL_JOBS)
+    for a_res, m_res in zip(alone, mixed):
+        w, gold = by_id[a_res.job_id]
+        ka, ca = a_res.sorted()
+        km, cm = m_res.sorted()
+        assert np.array_equal(ka, km) and np.array_equal(ca, cm), f"job {a_res.job_id}: alone and mixed differ"
+        assert np.array_equal(a_res.hist, m_res.hist)
+        assert a_res.n_valid == gold.int("n_valid")
+        assert np.array_equal(a_res.hist, _fold(gold.hist, a_res.hist.size))
+        assert ka.shape[0] == gold.int("n_pairs")
+        got = shard_digests_host(ka, ca, w.k, gold.int("shard_mod"))
+        assert [(n, d) for n, d in got] == [(n, d) for n, _, d in gold.shards], f"job {a_res.job_id}: pairs differ"
