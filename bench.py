@@ -7,7 +7,7 @@ BATCHED schedule (all bins in one persistent launch); the PLAIN schedule (one
 launch sequence per bin) is timed beside it on the same inputs. The unit of
 work is a valid (N-free) k-mer window.
 
-Prints ONE JSON line (see the design doc for every field).
+Prints ONE JSON line.
 """
 from __future__ import annotations
 
@@ -60,6 +60,10 @@ def parse_args(argv=None):
                     help="also evaluate the distinct-k-mer estimate of the paper's table sizing on the workload's bins")
     ap.add_argument("--orders", action="store_true",
                     help="also compare the minimizer orders of Sec. 3.1 on the workload (super-mers, bins, step time)")
+    ap.add_argument("--no-ceiling", action="store_true",
+                    help="skip the random-access and atomic ceilings of the device")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="threads of the all-core oracle leg (0: the usable cores, at most 16)")
     ap.add_argument("--parse", action="store_true",
                     help="also time FASTQ/FASTA parsing of the workload's reads on the device")
     return ap.parse_args(argv)
@@ -149,13 +153,38 @@ def percentile(xs, q):
     return s[i]
 
 
-def cpu_baseline(ascii_, offsets, k, threshold, target_s, canonical=True):
-    """The oracle as it stands, single-threaded, on a leading sample of reads."""
-    import numpy as np
+def host_description():
+    """Cores usable by this process, the CPU model and the RAM of the host."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    ram = None
+    try:
+        with open("/proc/meminfo") as f:
+            for ln in f:
+                if ln.startswith("MemTotal:"):
+                    ram = round(int(ln.split()[1]) * 1024 / 2 ** 30, 1)
+                    break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"nproc": usable, "cpu_count": os.cpu_count(), "cpu_model": model, "ram_gib": ram}
 
+
+def cpu_baseline(ascii_, offsets, k, threshold, target_s, canonical=True, threads=0):
+    """The oracle as it stands on a leading sample of reads: single-threaded
+    (oracle.count), then the same sample split into hash shards over every
+    usable core (oracle.count_sharded, one collecting thread per read range
+    and one sorting thread per shard). The all-core rate is the headline."""
     import oracle
     n_reads = offsets.size - 1
-    # calibrate on a small sample, then size the timed sample to ~target_s
+    # calibrate on a small sample, then size the timed sample to ~target_s of one core
     n0 = min(n_reads, 2000)
     t = time.perf_counter()
     r0 = oracle.count(ascii_, offsets[: n0 + 1], k, threshold=threshold, canonical=canonical)
@@ -166,10 +195,46 @@ def cpu_baseline(ascii_, offsets, k, threshold, target_s, canonical=True):
     n = int(min(n_reads, max(n0, want_windows / avg_windows)))
     t = time.perf_counter()
     r = oracle.count(ascii_, offsets[: n + 1], k, threshold=threshold, canonical=canonical)
-    dt = time.perf_counter() - t
-    return {"value": r.n_valid / dt, "unit": "k-mers/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n} of {n_reads} reads ({r.n_valid} valid windows), {dt:.1f} s single-threaded "
-                      f"sort-and-count"}
+    dt1 = time.perf_counter() - t
+    one = {"value": r.n_valid / dt1, "cores": 1, "seconds": round(dt1, 2)}
+    host = host_description()
+    T = threads or max(1, min(16, host["nproc"] or 1))
+    pairs = [0]
+
+    def on_shard(s, res):
+        pairs[0] += res.keys.shape[0]
+
+    t = time.perf_counter()
+    nv = oracle.count_sharded(ascii_, offsets[: n + 1], k, threshold, T, on_shard, canonical=canonical, group=0,
+                              threads=T, sort_workers=T)
+    dtT = time.perf_counter() - t
+    assert nv == r.n_valid and pairs[0] == r.keys.shape[0], "sharded oracle disagrees with the single-threaded one"
+    return {"value": nv / dtT, "unit": "k-mers/s", "cores": T, "kind": "oracle",
+            "sample": f"first {n} of {n_reads} reads ({r.n_valid} valid windows): {dtT:.1f} s on {T} threads "
+                      f"(hash shards, one per thread), {dt1:.1f} s single-threaded sort-and-count",
+            "single_core": one, "host": host}
+
+
+def device_ceilings():
+    """Random-access and atomic rates of the device (GERBIL_CEIL_*), in
+    operations per second, each the best of three timed launches."""
+    import torch
+
+    from paper_1607_06618_amd import gerbil as g
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    out = {}
+    for name, kind, grid, iters, buf in (
+            ("lds_cas64_per_s", g.GERBIL_CEIL_LDS_CAS, cus * 4, 256, 0),
+            ("lds_add32_per_s", g.GERBIL_CEIL_LDS_ADD, cus * 4, 256, 0),
+            ("hbm_add32_random_line_per_s", g.GERBIL_CEIL_HBM_ADD, cus * 8, 64, 4 << 30),
+            ("hbm_cas64_random_line_per_s", g.GERBIL_CEIL_HBM_CAS, cus * 8, 64, 4 << 30),
+            ("hbm_load64_random_line_per_s", g.GERBIL_CEIL_HBM_LOAD, cus * 8, 64, 4 << 30),
+            ("one_address_add_return_per_s", g.GERBIL_CEIL_ONE_ADDR, cus * 2, 256, 64)):
+        rate, ops, ms = g.ceiling(kind, grid, iters, buf_bytes=buf)
+        out[name] = float(f"{rate:.4g}")
+    torch.cuda.empty_cache()
+    print(f"[bench] device ceilings: {out}", file=sys.stderr, flush=True)
+    return out
 
 
 def main(argv=None):
@@ -338,7 +403,16 @@ def main(argv=None):
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(ascii_, offsets, w.k, w.threshold, args.cpu_seconds, canonical=not args.non_canonical)
+        cpu = cpu_baseline(ascii_, offsets, w.k, w.threshold, args.cpu_seconds, canonical=not args.non_canonical,
+                           threads=args.cpu_threads)
+    if not args.no_ceiling:
+        ceil = device_ceilings()
+        # every valid window is one insert of Alg. 1 into an LDS (or HBM) table
+        roofline["inserts_per_s"] = float(f"{n_valid / (R['kernel_ms'] / 1000.0):.4g}")
+        roofline["ceilings"] = ceil
+        key = "lds_cas64_per_s" if head_table == "lds" else "hbm_cas64_random_line_per_s"
+        roofline["inserts_frac_of_ceiling"] = round(roofline["inserts_per_s"] / ceil[key], 4)
+        roofline["ceiling_kind"] = key
 
     out = {
         "metric": METRIC, "value": value, "unit": "k-mers/s", "n_gpus": 1, "steps": args.steps,

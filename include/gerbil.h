@@ -487,6 +487,39 @@ int32_t gerbil_parse(const uint8_t* text, uint64_t n, uint32_t format, void* ws,
                      uint64_t lines_cap, uint8_t* seq, uint64_t seq_cap, uint64_t* offsets, uint64_t reads_cap,
                      gerbil_parsed* out, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Device ceilings (measurement only; nothing on the counting path uses
+ * them). Alg. 1 and the bucket scan of Sec. 3.3.1 are bound by random
+ * accesses and atomics, not by streaming, so inserts per second are
+ * reported next to the rates the device sustains for the same access kinds.
+ * ------------------------------------------------------------------------ */
+
+enum {
+    GERBIL_CEIL_LDS_CAS = 0,  /* 64-bit compare-and-swap with return, random slots of a 16384-slot
+                                 LDS table per workgroup (the claim of an LDS table insert)         */
+    GERBIL_CEIL_LDS_ADD = 1,  /* 32-bit add without return, random words of a 32768-word LDS array
+                                 per workgroup (the counter update)                                 */
+    GERBIL_CEIL_HBM_ADD = 2,  /* 32-bit device-scope add without return, random 64-byte lines of buf */
+    GERBIL_CEIL_HBM_CAS = 3,  /* 64-bit device-scope compare-and-swap with return, random lines     */
+    GERBIL_CEIL_HBM_LOAD = 4, /* 64-bit device-coherent load, random lines                           */
+    GERBIL_CEIL_ONE_ADDR = 5  /* device-scope add with return on the first word of buf, by lane 0 of
+                                 every wave (a shared work-queue cursor)                            */
+};
+
+/* One launch of `grid` workgroups of 1024 threads; each thread performs
+ * `iters` operations of `kind` at pseudo-random positions (ONE_ADDR: lane 0
+ * of each of the 16 waves of a workgroup performs `iters` dependent adds).
+ * Operations in the launch: grid * 1024 * iters (ONE_ADDR: grid * 16 * iters);
+ * the caller times the launch on `stream`.
+ *   buf    device memory for the HBM kinds and ONE_ADDR: buf_bytes >= 64, a
+ *          multiple of 64, 64-byte aligned; overwritten. NULL for the LDS kinds.
+ *   sink   device uint64 [grid * 1024]: one checksum per thread (so that no
+ *          operation is optimised away); overwritten.
+ * Asynchronous on `stream`. Errors: GERBIL_EINVAL (kind, sizes or pointers),
+ * GERBIL_EDEVICE (launch). */
+int32_t gerbil_ceiling(uint32_t kind, void* buf, uint64_t buf_bytes, uint32_t grid, uint32_t iters, uint64_t* sink,
+                       hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

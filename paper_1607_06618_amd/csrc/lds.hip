@@ -684,61 +684,101 @@ __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s
     }
 }
 
-// Alg. 1 in an LDS table of C slots (structure of arrays). One probe step per
-// loop iteration, so a lane that waits for a key being published by a lane
-// of its own wave retries only after that lane has finished publishing.
-template <int W>
-__device__ __forceinline__ bool lds_insert(uint64_t* w0, uint64_t* rest, uint32_t* cnt, uint32_t C, uint32_t theta,
-                                           const uint64_t (&key)[W], uint64_t h, uint32_t* status) {
-    if (key[0] == GERBIL_EMPTY) return false;   // the empty-slot marker (an all-T word) is never stored
+// Alg. 1 in an LDS table of C slots (structure of arrays) for the K keys a
+// lane holds, of which the first n are valid. One probe per loop iteration,
+// and a lane that settles a key starts its next key in the same iteration:
+// a wave then runs about as many iterations as its busiest lane has probes
+// in all, instead of, key after key, as many as its slowest lane needs for
+// that key. A lane that finds a key claimed but not yet published (by a lane
+// of its own wave) probes the same slot again in the next iteration, after
+// the claimer has published it. Keys whose theta probes fail, and keys whose
+// first word is the empty-slot marker (an all-T word, never stored), go to
+// the emergency area.
+template <int K, int W>
+__device__ __forceinline__ void lds_insert_all(const CountArgs& a, uint64_t* w0, uint64_t* rest, uint32_t* cnt,
+                                               uint32_t C, uint32_t theta, uint64_t (&key)[K][W], uint32_t n) {
     // C is prime and 1 <= step < C: double hashing visits theta distinct slots.
     // The sub-table is chosen by the top bits of h's low half and the slice by
     // the top bits of its high half, so the slot and the step take bits 0-19
     // and 32-51, which neither choice depends on.
-    const uint32_t step = 1u + fastrange32((uint32_t)((h >> 32) << 12), C - 1);
+    uint32_t sl[K], st[K];
+#pragma unroll
+    for (int e = 0; e < K; e++) {
+        const uint64_t h = key_hash<W>(key[e], a.seed);
+        st[e] = 1u + fastrange32((uint32_t)((h >> 32) << 12), C - 1);
+        sl[e] = fastrange32((uint32_t)(h << 12), C);
+    }
     uint32_t t = 0, spins = 0;
-    uint32_t sl = fastrange32((uint32_t)(h << 12), C);
-    for (;;) {
-        uint64_t cur = __hip_atomic_load(w0 + sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (cur == GERBIL_EMPTY) {
-            uint64_t exp = GERBIL_EMPTY;
-            __hip_atomic_compare_exchange_strong(w0 + sl, &exp, key[0], __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (exp == GERBIL_EMPTY) {
+    while (__ballot(n > 0) != 0ull) {
+        if (n > 0) {
+            bool settled = false;
+            if (key[0][0] == GERBIL_EMPTY) {
+                overflow_push<W>(a, key[0]);
+                settled = true;
+            } else {
+                const uint32_t s = sl[0];
+                uint64_t cur = __hip_atomic_load(w0 + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (cur == GERBIL_EMPTY) {
+                    uint64_t exp = GERBIL_EMPTY;
+                    __hip_atomic_compare_exchange_strong(w0 + s, &exp, key[0][0], __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if (exp == GERBIL_EMPTY) {
 #pragma unroll
-                for (int i = 1; i < W; i++) rest[(uint32_t)(i - 1) * C + sl] = key[i];
-                if (W > 1) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                __hip_atomic_fetch_add(cnt + sl, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                return true;
-            }
-            cur = exp;
-        }
-        if (cur == key[0]) {
-            if (W == 1) {
-                __hip_atomic_fetch_add(cnt + sl, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                return true;
-            }
-            uint32_t c = __hip_atomic_load(cnt + sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (c == 0) {
-                if (++spins > kLdsSpin) {
-                    set_status(status, ST_SPIN);
-                    return true;
+                        for (int i = 1; i < W; i++) rest[(uint32_t)(i - 1) * C + s] = key[0][i];
+                        if (W > 1) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                        __hip_atomic_fetch_add(cnt + s, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        settled = true;
+                    }
+                    cur = exp;
                 }
-                continue;   // published in the same iteration by its claimer; look again
-            }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            bool eq = true;
+                if (!settled) {
+                    bool again = false;   // same slot next iteration
+                    if (cur == key[0][0]) {
+                        if (W == 1) {
+                            __hip_atomic_fetch_add(cnt + s, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                            settled = true;
+                        } else if (__hip_atomic_load(cnt + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == 0) {
+                            again = true;
+                            if (++spins > kLdsSpin) {
+                                set_status(a.status, ST_SPIN);
+                                settled = true;
+                            }
+                        } else {
+                            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                            bool eq = true;
 #pragma unroll
-            for (int i = 1; i < W; i++) eq &= rest[(uint32_t)(i - 1) * C + sl] == key[i];
-            if (eq) {
-                // a run holds fewer than 2^32 keys, so a count cannot wrap
-                __hip_atomic_fetch_add(cnt + sl, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                return true;
+                            for (int i = 1; i < W; i++) eq &= rest[(uint32_t)(i - 1) * C + s] == key[0][i];
+                            if (eq) {
+                                // a run holds fewer than 2^32 keys, so a count cannot wrap
+                                __hip_atomic_fetch_add(cnt + s, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                                settled = true;
+                            }
+                        }
+                    }
+                    if (!settled && !again) {
+                        if (++t >= theta) {
+                            overflow_push<W>(a, key[0]);
+                            settled = true;
+                        } else {
+                            const uint32_t x = s + st[0];
+                            sl[0] = x >= C ? x - C : x;
+                        }
+                    }
+                }
+            }
+            if (settled) {
+                n--;
+                t = 0;
+                spins = 0;
+#pragma unroll
+                for (int e = 0; e + 1 < K; e++) {
+#pragma unroll
+                    for (int i = 0; i < W; i++) key[e][i] = key[e + 1][i];
+                    sl[e] = sl[e + 1];
+                    st[e] = st[e + 1];
+                }
             }
         }
-        if (++t >= theta) return false;
-        sl += step;
-        if (sl >= C) sl -= C;
     }
 }
 
@@ -795,19 +835,16 @@ __device__ void stage_table(const CountArgs& a, const LdsArgs& l, const Lds& s, 
 #pragma unroll
             for (int w = 0; w + 1 < W; w++) key[e][w] = ld_dev(&keys[(uint64_t)w * l.slot_keys + ix[e]]);
         load_tails<K, W>(tail, off, ix, l.tail_bytes, key);
-        uint32_t failed = 0;   // bit e: key e goes to the emergency area (pushed after the batch)
+        uint32_t nk = 0;   // valid keys of this lane: a prefix of the batch
 #pragma unroll
-        for (int e = 0; e < K; e++) {
-            const uint64_t i = base + (uint64_t)e * kLdsBlock + tid;
-            if (i < lim) {
-                if (spill || !lds_insert<W>(w0, rest, cnt, C, l.theta, key[e], key_hash<W>(key[e], a.seed), a.status))
-                    failed |= 1u << e;
-            }
-        }
-        if (failed) {
+        for (int e = 0; e < K; e++)
+            if (base + (uint64_t)e * kLdsBlock + tid < lim) nk = (uint32_t)e + 1;
+        if (spill) {
 #pragma unroll
             for (int e = 0; e < K; e++)
-                if (failed & (1u << e)) overflow_push<W>(a, key[e]);
+                if ((uint32_t)e < nk) overflow_push<W>(a, key[e]);
+        } else {
+            lds_insert_all<K, W>(a, w0, rest, cnt, C, l.theta, key, nk);
         }
     }
     __syncthreads();
@@ -819,13 +856,18 @@ __device__ void stage_table(const CountArgs& a, const LdsArgs& l, const Lds& s, 
     const uint32_t pre = block_excl_scan(mine, wsum, total);
     uint64_t base = 0;
     if (tid == 0 && total) base = add_dev(a.n_out, (uint64_t)total);
-    for (uint32_t sl = tid; sl < C; sl += kLdsBlock) {
-        const uint32_t c = cnt[sl];
-        if (c) {
+    // most distinct keys occur once: count those per wave with one LDS add
+    for (uint32_t b0 = 0; b0 < C; b0 += kLdsBlock) {
+        const uint32_t sl = b0 + tid;
+        const uint32_t c = sl < C ? cnt[sl] : 0u;
+        const uint64_t ones = __ballot(c == 1u);
+        if (ones && __lane_id() == (uint32_t)__ffsll((unsigned long long)ones) - 1u)
+            atomicAdd(&s.hist[1], (uint32_t)__popcll(ones));
+        if (c > 1u) {
             if (c < kLdsHist) atomicAdd(&s.hist[c], 1u);
             else add_dev(&a.hist[c < kHistInternal - 1 ? c : kHistInternal - 1], 1ull);
-            wmax = c > wmax ? c : wmax;
         }
+        wmax = c > wmax ? c : wmax;
     }
     if (tid == 0) *s_base = base;
     __syncthreads();

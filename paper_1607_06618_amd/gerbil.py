@@ -37,6 +37,12 @@ GERBIL_RANKS_DFP = 5
 GERBIL_TABLE_AUTO = 0
 GERBIL_TABLE_HBM = 1
 GERBIL_TABLE_LDS = 2
+GERBIL_CEIL_LDS_CAS = 0
+GERBIL_CEIL_LDS_ADD = 1
+GERBIL_CEIL_HBM_ADD = 2
+GERBIL_CEIL_HBM_CAS = 3
+GERBIL_CEIL_HBM_LOAD = 4
+GERBIL_CEIL_ONE_ADDR = 5
 GERBIL_FORMAT_DETECT = 0
 GERBIL_FORMAT_FASTQ = 1
 GERBIL_FORMAT_FASTA = 2
@@ -162,13 +168,14 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gerbil_hll_bins.argtypes = [P(gerbil_bins), P(gerbil_params), u32, vp, vp]
     lib.gerbil_order_table.argtypes = [u32, u32, u64, f32, u32, P(gerbil_encoded), vp, u64, vp, vp]
     lib.gerbil_parse.argtypes = [vp, u64, u32, vp, u64, u64, vp, u64, vp, u64, vp, vp]
+    lib.gerbil_ceiling.argtypes = [u32, vp, u64, u32, u32, vp, vp]
     for name in ("gerbil_encode_workspace", "gerbil_encode", "gerbil_bin_workspace", "gerbil_bin",
                  "gerbil_count_workspace", "gerbil_count", "gerbil_histogram", "gerbil_result",
                  "gerbil_graph_capture", "gerbil_graph_launch", "gerbil_graph_info", "gerbil_graph_destroy",
                  "gerbil_autotune_workspace", "gerbil_autotune", "gerbil_autotune_reset",
                  "gerbil_records_workspace", "gerbil_records", "gerbil_parse_workspace", "gerbil_parse",
                  "gerbil_order_table_workspace", "gerbil_order_table", "gerbil_key_bins",
-                 "gerbil_hll_bins"):
+                 "gerbil_hll_bins", "gerbil_ceiling"):
         getattr(lib, name).restype = ctypes.c_int32
     _lib = lib
     return lib
@@ -340,6 +347,35 @@ def key_bins(keys_d, n: int, params: gerbil_params, stream=None):
     bins = torch.empty(max(1, n), dtype=torch.int32, device=keys_d.device)
     check("gerbil_key_bins", gerbil_key_bins(keys_d.data_ptr(), n, params, bins.data_ptr(), _stream_handle(stream)))
     return bins[:n]
+
+
+def gerbil_ceiling(kind: int, buf_ptr: int, buf_bytes: int, grid: int, iters: int, sink_ptr: int,
+                   stream: int = 0) -> int:
+    return load().gerbil_ceiling(kind, buf_ptr or None, buf_bytes, grid, iters, sink_ptr or None, stream)
+
+
+def ceiling(kind: int, grid: int, iters: int, buf_bytes: int = 0, repeats: int = 3, device="cuda"):
+    """Operations per second of one access kind (GERBIL_CEIL_*): the best of
+    `repeats` timed launches after one warm-up, timed with HIP events on the
+    current stream. Returns (ops_per_s, ops_per_launch, ms_per_launch)."""
+    import torch
+    s = torch.cuda.current_stream()
+    h = _stream_handle(s)
+    sink = torch.empty(grid * 1024, dtype=torch.int64, device=device)
+    buf = torch.zeros(max(64, buf_bytes) // 8, dtype=torch.int64, device=device) if buf_bytes else None
+    bp, bb = (buf.data_ptr(), buf.numel() * 8) if buf is not None else (0, 0)
+    ops = grid * (16 if kind == GERBIL_CEIL_ONE_ADDR else 1024) * iters
+    check("gerbil_ceiling", gerbil_ceiling(kind, bp, bb, grid, iters, sink.data_ptr(), h))
+    best = None
+    for _ in range(repeats):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        check("gerbil_ceiling", gerbil_ceiling(kind, bp, bb, grid, iters, sink.data_ptr(), h))
+        e1.record(s)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    return ops / (best * 1e-3), ops, best
 
 
 def gerbil_order_table_workspace(kind: int, m: int) -> int:

@@ -199,3 +199,18 @@ def test_key_bins_and_hll_validation():
     assert g.gerbil_hll_bins(bins, p, 12, 0) == g.GERBIL_EINVAL
     assert g.gerbil_hll_bins(bins, g.make_params(33, 9, 64, 1), 12, fake) == g.GERBIL_EINVAL   # k differs
     assert g.gerbil_hll_bins(g.gerbil_bins(k=65, n_bins=64), p, 12, fake) == g.GERBIL_EINVAL  # no bins
+
+
+def test_ceiling_validation_before_launch():
+    # every argument error is returned before anything is enqueued (no GPU needed)
+    sink = 4096
+    assert g.gerbil_ceiling(g.GERBIL_CEIL_LDS_CAS, 0, 0, 1, 1, 0) == g.GERBIL_EINVAL          # no sink
+    assert g.gerbil_ceiling(g.GERBIL_CEIL_LDS_CAS, 0, 0, 0, 1, sink) == g.GERBIL_EINVAL       # empty grid
+    assert g.gerbil_ceiling(g.GERBIL_CEIL_LDS_CAS, 0, 0, 1, 0, sink) == g.GERBIL_EINVAL       # no iterations
+    assert g.gerbil_ceiling(6, 0, 0, 1, 1, sink) == g.GERBIL_EINVAL                          # unknown kind
+    for kind in (g.GERBIL_CEIL_HBM_ADD, g.GERBIL_CEIL_HBM_CAS, g.GERBIL_CEIL_HBM_LOAD, g.GERBIL_CEIL_ONE_ADDR):
+        assert g.gerbil_ceiling(kind, 0, 4096, 1, 1, sink) == g.GERBIL_EINVAL                # no buffer
+        assert g.gerbil_ceiling(kind, 4096, 32, 1, 1, sink) == g.GERBIL_EINVAL               # under one line
+        assert g.gerbil_ceiling(kind, 4096, 100, 1, 1, sink) == g.GERBIL_EINVAL              # not whole lines
+        assert g.gerbil_ceiling(kind, 4100, 4096, 1, 1, sink) == g.GERBIL_EINVAL             # misaligned
+
