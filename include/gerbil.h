@@ -373,6 +373,26 @@ int32_t gerbil_records_workspace(uint64_t n, uint64_t* bytes);
 int32_t gerbil_records(const uint64_t* keys, const uint32_t* counts, uint64_t n, uint32_t k, void* ws,
                        uint64_t ws_bytes, uint8_t* out, uint64_t out_cap, uint64_t* out_bytes, hipStream_t stream);
 
+/* Largest n that gerbil_records_noalloc takes: 2^29 pairs (65536 tiles of 8192). */
+#define GERBIL_RECORDS_NOALLOC_MAX 536870912ull
+
+/* gerbil_records without a workspace, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation. Nothing is allocated by this call or by the library for
+ * it (no hipMalloc, no allocating library routine): the per-tile scratch that
+ * gerbil_records keeps in its workspace lives in one static device array of
+ * the library, 786,688 bytes on each GPU that calls it, held until the process
+ * ends. Arguments and results are those of gerbil_records (the caller still
+ * provides keys, counts, out and out_bytes), with n <= GERBIL_RECORDS_NOALLOC_MAX.
+ * The scratch of a GPU is shared by every call on that GPU and keeps the last
+ * call's contents (each call writes every entry it reads): calls that overlap
+ * on one GPU (on different streams, or from different threads) race and must
+ * be serialised by the caller. The first call on a device looks up the
+ * array's address on that device (synchronous; not a stream operation).
+ * Errors: GERBIL_EINVAL (bad arguments, n above the maximum), GERBIL_EDEVICE. */
+int32_t gerbil_records_noalloc(const uint64_t* keys, const uint32_t* counts, uint64_t n, uint32_t k, uint8_t* out,
+                               uint64_t out_cap, uint64_t* out_bytes, hipStream_t stream);
+
 /* Bin of each of n keys (the layout gerbil_count emits) under the binning of
  * `p` (k, m, n_bins, order, bin_map, rank_table): the bin that gerbil_bin
  * sends every occurrence of the key to (Sec. 2.1, Sec. 3.1). With counts of

@@ -9,6 +9,8 @@
 // scan of the tile totals, then per tile and round the records are built in
 // LDS and the round's byte range is copied out with consecutive lanes on
 // consecutive bytes.
+#include <mutex>
+
 #include "../../include/gerbil.h"
 #include "table.h"
 
@@ -134,6 +136,65 @@ __global__ void __launch_bounds__(kRecBlock) k_rec_write(const uint64_t* __restr
     }
 }
 
+// Workspace bytes for n_tiles tiles: the large-counter count per tile, then
+// the large counters before each tile.
+constexpr uint64_t rec_ws_bytes(uint64_t n_tiles) { return 256 + ((4 * n_tiles + 255) & ~255ull) + 8 * n_tiles; }
+
+hipError_t enqueue_records(const uint64_t* keys, const uint32_t* counts, uint64_t n, uint32_t k, uint8_t* ws,
+                           uint8_t* out, uint64_t out_cap, uint64_t* out_bytes, hipStream_t stream) {
+    const uint32_t W = (k + 31) / 32, kb = (k + 3) / 4;
+    if (n == 0) return launch_fill_u64(out_bytes, 1, 0ull, stream);
+    const uint64_t n_tiles = (n + kRecTile - 1) / kRecTile;
+    uint32_t* tile_big = (uint32_t*)(ws + 256);
+    uint64_t* tile_base = (uint64_t*)(ws + 256 + ((4 * n_tiles + 255) & ~255ull));
+    const uint32_t grid = (uint32_t)(n_tiles < 4096 ? n_tiles : 4096);
+    hipLaunchKernelGGL(k_rec_flags, dim3(grid), dim3(kRecBlock), 0, stream, counts, n, tile_big);
+    hipLaunchKernelGGL(k_rec_scan, dim3(1), dim3(kRecBlock), 0, stream, tile_big, n_tiles, tile_base, n, kb, out_bytes);
+    const uint32_t lds = kRecBlock * (5 + kb);   // up to 69 KB: above the default dynamic LDS limit
+    // set on every call: the attribute belongs to the current device's module
+    hipError_t e = hipFuncSetAttribute((const void*)k_rec_write, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rec_write, dim3(grid), dim3(kRecBlock), lds, stream, keys, counts, n, k, W, tile_base, out,
+                       out_cap);
+    return hipGetLastError();
+}
+
+// The allocation-free variant keeps the workspace in a static device array
+// of the library: one copy per GPU, at that GPU's own address, which the host
+// learns once per device with hipGetSymbolAddress. The array's name in host
+// code is only a host-side stand-in and is never passed to a kernel.
+constexpr uint64_t kNoAllocTiles = GERBIL_RECORDS_NOALLOC_MAX / kRecTile;
+static_assert(GERBIL_RECORDS_NOALLOC_MAX % kRecTile == 0, "the pair limit is whole tiles");
+constexpr uint64_t kScratchBytes = rec_ws_bytes(kNoAllocTiles);
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up once per device).
+hipError_t scratch_address(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return hipSuccess;
+}
+
 }  // namespace
 }  // namespace gerbil
 
@@ -143,8 +204,7 @@ extern "C" {
 
 int32_t gerbil_records_workspace(uint64_t n, uint64_t* bytes) {
     if (!bytes) return GERBIL_EINVAL;
-    const uint64_t n_tiles = (n + kRecTile - 1) / kRecTile;
-    *bytes = 256 + ((4 * n_tiles + 255) & ~255ull) + 8 * n_tiles;
+    *bytes = rec_ws_bytes((n + kRecTile - 1) / kRecTile);
     return GERBIL_OK;
 }
 
@@ -152,25 +212,21 @@ int32_t gerbil_records(const uint64_t* keys, const uint32_t* counts, uint64_t n,
                        uint64_t ws_bytes, uint8_t* out, uint64_t out_cap, uint64_t* out_bytes, hipStream_t stream) {
     if (!out_bytes || k < 1 || k > 32 * GERBIL_MAX_W) return GERBIL_EINVAL;
     if (n && (!keys || !counts || !ws || (out_cap && !out))) return GERBIL_EINVAL;
-    uint64_t need = 0;
-    gerbil_records_workspace(n, &need);
-    if (n && (ws_bytes < need || (((uintptr_t)ws) & 255))) return GERBIL_EINVAL;
-    const uint32_t W = (k + 31) / 32, kb = (k + 3) / 4;
-    if (n == 0) return launch_fill_u64(out_bytes, 1, 0ull, stream) == hipSuccess ? GERBIL_OK : GERBIL_EDEVICE;
-    const uint64_t n_tiles = (n + kRecTile - 1) / kRecTile;
-    uint32_t* tile_big = (uint32_t*)((uint8_t*)ws + 256);
-    uint64_t* tile_base = (uint64_t*)((uint8_t*)ws + 256 + ((4 * n_tiles + 255) & ~255ull));
-    const uint32_t grid = (uint32_t)(n_tiles < 4096 ? n_tiles : 4096);
-    hipLaunchKernelGGL(k_rec_flags, dim3(grid), dim3(kRecBlock), 0, stream, counts, n, tile_big);
-    hipLaunchKernelGGL(k_rec_scan, dim3(1), dim3(kRecBlock), 0, stream, tile_big, n_tiles, tile_base, n, kb, out_bytes);
-    const uint32_t lds = kRecBlock * (5 + kb);   // up to 69 KB: above the default dynamic LDS limit
-    // set on every call: the attribute belongs to the current device's module
-    if (hipFuncSetAttribute((const void*)k_rec_write, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
-        hipSuccess)
-        return GERBIL_EDEVICE;
-    hipLaunchKernelGGL(k_rec_write, dim3(grid), dim3(kRecBlock), lds, stream, keys, counts, n, k, W, tile_base, out,
-                       out_cap);
-    return hipGetLastError() == hipSuccess ? GERBIL_OK : GERBIL_EDEVICE;
+    if (n && (ws_bytes < rec_ws_bytes((n + kRecTile - 1) / kRecTile) || (((uintptr_t)ws) & 255))) return GERBIL_EINVAL;
+    return enqueue_records(keys, counts, n, k, (uint8_t*)ws, out, out_cap, out_bytes, stream) == hipSuccess
+               ? GERBIL_OK
+               : GERBIL_EDEVICE;
+}
+
+int32_t gerbil_records_noalloc(const uint64_t* keys, const uint32_t* counts, uint64_t n, uint32_t k, uint8_t* out,
+                               uint64_t out_cap, uint64_t* out_bytes, hipStream_t stream) {
+    if (!out_bytes || k < 1 || k > 32 * GERBIL_MAX_W || n > GERBIL_RECORDS_NOALLOC_MAX) return GERBIL_EINVAL;
+    if (n && (!keys || !counts || (out_cap && !out))) return GERBIL_EINVAL;
+    void* ws = nullptr;
+    if (scratch_address(&ws) != hipSuccess) return GERBIL_EDEVICE;
+    return enqueue_records(keys, counts, n, k, (uint8_t*)ws, out, out_cap, out_bytes, stream) == hipSuccess
+               ? GERBIL_OK
+               : GERBIL_EDEVICE;
 }
 
 }  // extern "C"

@@ -162,6 +162,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gerbil_autotune_reset.argtypes = []
     lib.gerbil_records_workspace.argtypes = [u64, P(u64)]
     lib.gerbil_records.argtypes = [vp, vp, u64, u32, vp, u64, vp, u64, vp, vp]
+    lib.gerbil_records_noalloc.argtypes = [vp, vp, u64, u32, vp, u64, vp, vp]
     lib.gerbil_parse_workspace.argtypes = [u64, u64, P(u64)]
     lib.gerbil_order_table_workspace.argtypes = [u32, u32, P(u64)]
     lib.gerbil_key_bins.argtypes = [vp, u64, P(gerbil_params), vp, vp]
@@ -173,7 +174,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                  "gerbil_count_workspace", "gerbil_count", "gerbil_histogram", "gerbil_result",
                  "gerbil_graph_capture", "gerbil_graph_launch", "gerbil_graph_info", "gerbil_graph_destroy",
                  "gerbil_autotune_workspace", "gerbil_autotune", "gerbil_autotune_reset",
-                 "gerbil_records_workspace", "gerbil_records", "gerbil_parse_workspace", "gerbil_parse",
+                 "gerbil_records_workspace", "gerbil_records", "gerbil_records_noalloc", "gerbil_parse_workspace", "gerbil_parse",
                  "gerbil_order_table_workspace", "gerbil_order_table", "gerbil_key_bins",
                  "gerbil_hll_bins", "gerbil_ceiling"):
         getattr(lib, name).restype = ctypes.c_int32
@@ -305,6 +306,15 @@ def gerbil_records(keys_ptr: int, counts_ptr: int, n: int, k: int, ws_ptr: int, 
                    out_cap: int, out_bytes_ptr: int, stream: int = 0) -> int:
     return load().gerbil_records(keys_ptr or None, counts_ptr or None, n, k, ws_ptr or None, ws_bytes,
                                  out_ptr or None, out_cap, out_bytes_ptr, stream)
+
+
+GERBIL_RECORDS_NOALLOC_MAX = 1 << 29
+
+
+def gerbil_records_noalloc(keys_ptr: int, counts_ptr: int, n: int, k: int, out_ptr: int, out_cap: int,
+                           out_bytes_ptr: int, stream: int = 0) -> int:
+    return load().gerbil_records_noalloc(keys_ptr or None, counts_ptr or None, n, k, out_ptr or None, out_cap,
+                                         out_bytes_ptr or None, stream)
 
 
 def records(keys_d, counts_d, n: int, k: int, stream=None):

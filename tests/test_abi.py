@@ -214,3 +214,13 @@ def test_ceiling_validation_before_launch():
         assert g.gerbil_ceiling(kind, 4096, 100, 1, 1, sink) == g.GERBIL_EINVAL              # not whole lines
         assert g.gerbil_ceiling(kind, 4100, 4096, 1, 1, sink) == g.GERBIL_EINVAL             # misaligned
 
+
+def test_records_noalloc_validation_before_launch():
+    # argument errors come back before the scratch is looked up or anything is enqueued
+    size = 4096
+    assert g.gerbil_records_noalloc(8, 8, 1, 65, 8, 8, 0) == g.GERBIL_EINVAL                  # no out_bytes
+    assert g.gerbil_records_noalloc(8, 8, 1, 0, 8, 8, size) == g.GERBIL_EINVAL                # k = 0
+    assert g.gerbil_records_noalloc(8, 8, 1, 481, 8, 8, size) == g.GERBIL_EINVAL              # k too long
+    assert g.gerbil_records_noalloc(0, 8, 1, 65, 8, 8, size) == g.GERBIL_EINVAL               # no keys
+    assert g.gerbil_records_noalloc(8, 8, 1, 65, 0, 8, size) == g.GERBIL_EINVAL               # no output
+    assert g.gerbil_records_noalloc(8, 8, g.GERBIL_RECORDS_NOALLOC_MAX + 1, 65, 8, 8, size) == g.GERBIL_EINVAL
