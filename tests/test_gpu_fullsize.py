@@ -55,6 +55,8 @@ def check_against_golden(name, job, gold, W, k):
 @pytest.mark.parametrize("name,tune", [("c2_k65", False), ("c3_skew", True), ("c4_longk", False)])
 def test_full_size_workload(name, tune):
     import torch
+    if not os.path.exists(fullsize.golden_path(name)):
+        pytest.skip(f"no oracle digest for {name} yet: run tests/golden/fullsize.py {name}")
     gold = fullsize.read(name)
     w = synth.CONFIGS[name]
     a, o = w.generate(threads=16)
