@@ -242,7 +242,10 @@ int32_t gerbil_count_workspace(const gerbil_bins* bins, const gerbil_params* p, 
 int32_t gerbil_count(const gerbil_bins* bins, const gerbil_params* p, void* ws, uint64_t ws_bytes,
                      uint64_t* keys, uint32_t* counts, uint64_t cap, gerbil_counted* state, hipStream_t stream);
 
-/* Count-of-counts over every distinct canonical k-mer, before the threshold:
+/* Count-of-counts over every distinct canonical k-mer, before the threshold
+ * (the k-mer histogram of the problem statement, Sec. 1, and of the `-x h`
+ * option of App. A, read as the number of k-mers per count value so that
+ * sum_c c * hist[c] equals the number of valid windows):
  * hist[c] = number of k-mers with count c for 1 <= c < len-1, hist[len-1] =
  * number with count >= len-1, hist[0] = 0.
  *   hist     device uint64 [len], 2 <= len <= 65536 */
@@ -310,7 +313,7 @@ int32_t gerbil_graph_destroy(gerbil_graph* g);
 
 /* ------------------------------------------------------------------------
  * Autotuner. The paper chooses thread counts at run time and re-estimates
- * table sizes from the data (Sec. 2.3; Sec. 3.4.2); here the schedule's
+ * table sizes from the data (Sec. 2.3; Sec. 3.4.1); here the schedule's
  * free parameters are chosen by timing them on the caller's bins.
  * ------------------------------------------------------------------------ */
 
@@ -455,7 +458,7 @@ int32_t gerbil_order_table(uint32_t kind, uint32_t m, uint64_t seed, float pivot
                            hipStream_t stream);
 
 /* ------------------------------------------------------------------------
- * Input parsing (the formats of App. C): FASTA or FASTQ text in device
+ * Input parsing (the formats of App. B): FASTA or FASTQ text in device
  * memory to the CSR reads gerbil_encode takes.
  * ------------------------------------------------------------------------ */
 
@@ -483,7 +486,7 @@ typedef struct {
 /* Workspace bytes of gerbil_parse for n text bytes and up to lines_cap lines. */
 int32_t gerbil_parse_workspace(uint64_t n, uint64_t lines_cap, uint64_t* bytes);
 
-/* Parse FASTA or FASTQ text (the input formats named in App. C; compressed
+/* Parse FASTA or FASTQ text (the input formats named in App. B; compressed
  * and staden inputs are not handled). Lines end at '\n'; a final line may
  * lack it; one '\r' right before a line's end is dropped. FASTQ: records of
  * four lines ('@' header, sequence, '+' line, quality of the sequence's

@@ -22,6 +22,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gerbil_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# A test may point the oracle at another build of gerbil_oracle.c (the
+# mutation test loads deliberately broken copies this way); it is never built here.
+_LIB_OVERRIDE = os.environ.get("ORACLE_LIBRARY")
 _lib = None
 
 
@@ -49,9 +52,12 @@ class _Result(ctypes.Structure):
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build(force=True)
-        lib = ctypes.CDLL(_LIB)
+        if _LIB_OVERRIDE:
+            lib = ctypes.CDLL(_LIB_OVERRIDE)
+        else:
+            if not os.path.exists(_LIB):
+                build(force=True)
+            lib = ctypes.CDLL(_LIB)
         vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
         lib.oracle_count.argtypes = [vp, vp, u64, u32, u32, u32, u64, u64, ctypes.POINTER(_Result)]
         lib.oracle_count.restype = i32
@@ -383,7 +389,7 @@ class Parsed:
 
 
 def parse_reads(text: bytes, fmt: int = 0) -> Parsed:
-    """Reads of a FASTA or FASTQ text (the input formats of App. C), as the
+    """Reads of a FASTA or FASTQ text (the input formats of App. B), as the
     CSR arrays the encoder takes.
 
     Lines end at a newline; a final line may lack one; one carriage return

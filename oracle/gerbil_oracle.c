@@ -231,7 +231,7 @@ int oracle_count_multiset(uint64_t* all, uint64_t n, uint32_t W, uint32_t thresh
     out->n_valid_shard = n;
 
     /* Step 6: sort the multiset, then run-length it. */
-    qsort_r(all, n, 8 * W, cmp_keys, &W);
+    if (n) qsort_r(all, n, 8 * W, cmp_keys, &W);   /* an empty shard may come with no array at all */
     uint64_t n_distinct = 0, max_count = 0;
     for (uint64_t i = 0; i < n;) {
         uint64_t j = i + 1;

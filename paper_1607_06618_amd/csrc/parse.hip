@@ -1,5 +1,5 @@
 // FASTA / FASTQ text to CSR reads, on the device (the input formats of
-// App. C; the paper's parser stage feeds the counting pipeline, Sec. 3).
+// App. B; the paper's parser stage feeds the counting pipeline, Sec. 2.3.1).
 //
 // The text is cut into lines by a newline compaction; every later step works
 // on lines, never on the text again, except for the copy of the sequence

@@ -4,7 +4,7 @@
 // are cached per (device, key width, m, bins, schedule, bin-size profile),
 // so later runs of the same shape skip the timing. The paper picks thread
 // counts at run time and re-estimates table sizes per file (Sec. 2.3,
-// Sec. 3.4.2); here the device-side analogs are tuned by measurement.
+// Sec. 3.4.1); here the device-side analogs are tuned by measurement.
 #include <math.h>
 #include <string.h>
 
