@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <vector>
 
@@ -40,16 +41,20 @@ struct Carve {
 
 uint32_t words_for(uint32_t k) { return (k + 31) / 32; }
 
+// Compute units of the current device (looked up per device, once).
 int device_cus() {
-    static int cus = 0;
-    if (!cus) {
-        int dev = 0;
+    constexpr int kMaxDev = 64;
+    static std::atomic<int> cus[kMaxDev];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) return 256;
+    int c = cus[dev].load(std::memory_order_relaxed);
+    if (!c) {
         hipDeviceProp_t prop;
-        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-            cus = prop.multiProcessorCount;
-        if (cus <= 0) cus = 256;
+        c = hipGetDeviceProperties(&prop, dev) == hipSuccess ? prop.multiProcessorCount : 0;
+        if (c <= 0) c = 256;
+        cus[dev].store(c, std::memory_order_relaxed);
     }
-    return cus;
+    return c;
 }
 
 uint64_t next_pow2(uint64_t x) {

@@ -19,6 +19,8 @@
 //     flags a device error when it gives up.
 // Inserts of one bin and dumps of another overlap on the device, and no
 // launch gaps or per-bin tails remain.
+#include <atomic>
+
 #include "table.h"
 
 namespace gerbil {
@@ -240,9 +242,9 @@ static uint32_t occupancy_w() {
 
 uint32_t persistent_blocks_per_cu(uint32_t W, uint32_t block) {
     (void)block;
-    static uint32_t cached[GERBIL_MAX_W + 1] = {0};
+    static std::atomic<uint32_t> cached[GERBIL_MAX_W + 1];   // zero-initialised; same value from any thread
     if (W < 1 || W > GERBIL_MAX_W) return 1;
-    if (cached[W]) return cached[W];
+    if (const uint32_t c = cached[W].load(std::memory_order_relaxed)) return c;
     uint32_t r = 1;
     switch (W) {
         case 1: r = occupancy_w<1>(); break;
@@ -261,7 +263,7 @@ uint32_t persistent_blocks_per_cu(uint32_t W, uint32_t block) {
         case 14: r = occupancy_w<14>(); break;
         case 15: r = occupancy_w<15>(); break;
     }
-    cached[W] = r;
+    cached[W].store(r, std::memory_order_relaxed);
     return r;
 }
 

@@ -689,11 +689,14 @@ __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s
 // and a lane that settles a key starts its next key in the same iteration:
 // a wave then runs about as many iterations as its busiest lane has probes
 // in all, instead of, key after key, as many as its slowest lane needs for
-// that key. A lane that finds a key claimed but not yet published (by a lane
-// of its own wave) probes the same slot again in the next iteration, after
-// the claimer has published it. Keys whose theta probes fail, and keys whose
-// first word is the empty-slot marker (an all-T word, never stored), go to
-// the emergency area.
+// that key. A probe reads the slot's probe word, counter and other words in
+// one batch: the wave's LDS accesses are performed in order, and a claimer
+// writes the other words before it raises the counter from zero, so a
+// counter found non-zero guarantees that the words read after it are the
+// slot's key. A slot found claimed but not yet published, or lost to
+// another claimer, is probed again in the next iteration. Keys whose theta
+// probes fail, and keys whose first word is the empty-slot marker (an all-T
+// word, never stored), go to the emergency area.
 template <int K, int W>
 __device__ __forceinline__ void lds_insert_all(const CountArgs& a, uint64_t* w0, uint64_t* rest, uint32_t* cnt,
                                                uint32_t C, uint32_t theta, uint64_t (&key)[K][W], uint32_t n) {
@@ -708,6 +711,7 @@ __device__ __forceinline__ void lds_insert_all(const CountArgs& a, uint64_t* w0,
         st[e] = 1u + fastrange32((uint32_t)((h >> 32) << 12), C - 1);
         sl[e] = fastrange32((uint32_t)(h << 12), C);
     }
+    constexpr int RW = W > 1 ? W - 1 : 1;
     uint32_t t = 0, spins = 0;
     while (__ballot(n > 0) != 0ull) {
         if (n > 0) {
@@ -717,7 +721,18 @@ __device__ __forceinline__ void lds_insert_all(const CountArgs& a, uint64_t* w0,
                 settled = true;
             } else {
                 const uint32_t s = sl[0];
-                uint64_t cur = __hip_atomic_load(w0 + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                const uint64_t cur = __hip_atomic_load(w0 + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                uint32_t c = 1;
+                uint64_t rw[RW];
+                if (W > 1) {
+                    c = __hip_atomic_load(cnt + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    asm volatile("" ::: "memory");   // the other words are read after the counter
+#pragma unroll
+                    for (int i = 0; i + 1 < W; i++)
+                        rw[i] = __hip_atomic_load(rest + (uint32_t)i * C + s, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+                bool again = false;   // same slot next iteration
                 if (cur == GERBIL_EMPTY) {
                     uint64_t exp = GERBIL_EMPTY;
                     __hip_atomic_compare_exchange_strong(w0 + s, &exp, key[0][0], __ATOMIC_RELAXED, __ATOMIC_RELAXED,
@@ -728,41 +743,32 @@ __device__ __forceinline__ void lds_insert_all(const CountArgs& a, uint64_t* w0,
                         if (W > 1) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                         __hip_atomic_fetch_add(cnt + s, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                         settled = true;
+                    } else {
+                        again = true;
                     }
-                    cur = exp;
-                }
-                if (!settled) {
-                    bool again = false;   // same slot next iteration
-                    if (cur == key[0][0]) {
-                        if (W == 1) {
-                            __hip_atomic_fetch_add(cnt + s, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                            settled = true;
-                        } else if (__hip_atomic_load(cnt + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == 0) {
-                            again = true;
-                            if (++spins > kLdsSpin) {
-                                set_status(a.status, ST_SPIN);
-                                settled = true;
-                            }
-                        } else {
-                            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                            bool eq = true;
+                } else if (cur == key[0][0]) {
+                    bool eq = c != 0;
 #pragma unroll
-                            for (int i = 1; i < W; i++) eq &= rest[(uint32_t)(i - 1) * C + s] == key[0][i];
-                            if (eq) {
-                                // a run holds fewer than 2^32 keys, so a count cannot wrap
-                                __hip_atomic_fetch_add(cnt + s, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                                settled = true;
-                            }
+                    for (int i = 0; i + 1 < W; i++) eq &= rw[i] == key[0][i + 1];
+                    if (eq) {
+                        // a run holds fewer than 2^32 keys, so a count cannot wrap
+                        __hip_atomic_fetch_add(cnt + s, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        settled = true;
+                    } else if (c == 0) {
+                        again = true;
+                        if (++spins > kLdsSpin) {
+                            set_status(a.status, ST_SPIN);
+                            settled = true;
                         }
                     }
-                    if (!settled && !again) {
-                        if (++t >= theta) {
-                            overflow_push<W>(a, key[0]);
-                            settled = true;
-                        } else {
-                            const uint32_t x = s + st[0];
-                            sl[0] = x >= C ? x - C : x;
-                        }
+                }
+                if (!settled && !again) {
+                    if (++t >= theta) {
+                        overflow_push<W>(a, key[0]);
+                        settled = true;
+                    } else {
+                        const uint32_t x = s + st[0];
+                        sl[0] = x >= C ? x - C : x;
                     }
                 }
             }
@@ -1036,15 +1042,14 @@ __global__ void __launch_bounds__(kLdsBlock) k_lds_stage(CountArgs a, LdsArgs l,
     hist_end(a, s, wmax);
 }
 
+// The LDS attribute is set on every launch: it belongs to the current device's
+// module, and a process-wide "already set" flag would race between threads
+// and miss other devices.
 template <int W>
 static hipError_t persistent_lds_w(const CountArgs& a, const LdsArgs& l, uint32_t grid, hipStream_t s) {
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_lds_persistent<W>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
+    hipError_t e = hipFuncSetAttribute((const void*)k_lds_persistent<W>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       kLdsBytes);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_lds_persistent<W>, dim3(grid), dim3(kLdsBlock), kLdsBytes, s, a, l);
     return hipGetLastError();
 }
@@ -1052,14 +1057,10 @@ static hipError_t persistent_lds_w(const CountArgs& a, const LdsArgs& l, uint32_
 template <int W>
 static hipError_t stage_lds_w(const CountArgs& a, const LdsArgs& l, uint32_t st, uint32_t r, uint32_t items,
                               hipStream_t s) {
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_lds_stage<W>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           kLdsBytes);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
     if (items == 0) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute((const void*)k_lds_stage<W>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       kLdsBytes);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_lds_stage<W>, dim3(items), dim3(kLdsBlock), kLdsBytes, s, a, l, st, r);
     return hipGetLastError();
 }
