@@ -40,15 +40,21 @@ def parse_args(argv=None):
     ap.add_argument("--pool", type=int, default=0)
     ap.add_argument("--load", type=float, default=0.0)
     ap.add_argument("--table", default="lds", choices=["lds", "hbm"])
+    ap.add_argument("--block", type=int, default=0,
+                    help="threads per counting workgroup (LDS tables: 512 = two workgroups per CU)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tune", action="store_true", help="autotune the batched schedule before timing it")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes three times (calibrates HBM byte counters)")
     ap.add_argument("--stage-clocks", action="store_true", help="report busy time per LDS stage (batched)")
+    ap.add_argument("--probes", action="store_true",
+                    help="report how many probes LDS-table inserts took (batched; the statistic of Sec. 3.3.1)")
     ap.add_argument("--serving", type=int, default=0, help="also serve this many jobs of the Poisson job stream")
     ap.add_argument("--serving-scale", type=float, default=1.0, help="genome-size scale of the served jobs")
     ap.add_argument("--serving-inflight", type=int, default=4)
+    ap.add_argument("--serving-distinct", type=int, default=24,
+                    help="distinct job payloads the serving stream cycles through")
     ap.add_argument("--size-sample", type=int, default=0,
                     help="LDS run sizing: every n-th segment is counted (0 = library default, 1 = exact)")
     ap.add_argument("--k", type=int, default=0, help="override the workload's k (keys above 256 bases use HBM tables)")
@@ -292,6 +298,7 @@ def main(argv=None):
         if w.k > 256 and args.table == "lds":
             table = g.GERBIL_TABLE_HBM   # LDS tables hold keys of up to 256 bases
         p = g.make_params(w.k, w.m, w.n_bins, w.threshold, mode=mode, pool=args.pool, load_factor=args.load, table=table,
+                          block=args.block,
                           canonical=not args.non_canonical, size_sample=args.size_sample,
                           bin_map_ptr=bin_map_d.data_ptr() if bin_map_d is not None else 0,
                           timing_events=ctypes.addressof(ev))
@@ -299,6 +306,10 @@ def main(argv=None):
         if args.stage_clocks and mode == g.GERBIL_BATCHED and not graph:
             clocks_d = torch.zeros(8, dtype=torch.int64, device=dev)
             p.stage_clocks = clocks_d.data_ptr()
+        probes_d = None
+        if args.probes and mode == g.GERBIL_BATCHED and not graph:
+            probes_d = torch.zeros(g.GERBIL_PROBE_HIST, dtype=torch.int64, device=dev)
+            p.probe_hist = probes_d.data_ptr()
         with torch.cuda.stream(stream):
             job = g.Job(ascii_d, offsets_d, int(offsets[-1]), p, hist_len=65536, stream=stream)
             # first pass sizes the workspaces (synchronises); outputs are shared between schedules
@@ -311,7 +322,7 @@ def main(argv=None):
             if args.tune and mode == g.GERBIL_BATCHED:
                 info = job.autotune()
                 tune = {"table": {g.GERBIL_TABLE_LDS: "lds", g.GERBIL_TABLE_HBM: "hbm"}[info.table],
-                        "load_factor": round(info.load_factor, 3), "pool": info.pool,
+                        "load_factor": round(info.load_factor, 3), "pool": info.pool, "block": info.block,
                         "candidates": info.candidates, "cached": bool(info.cached),
                         "best_count_ms": round(info.best_ms, 3)}
                 print(f"[bench] {mode_name} autotune: {tune}", file=sys.stderr, flush=True)
@@ -351,6 +362,18 @@ def main(argv=None):
             kms = sum(kms_all) / len(kms_all)
         results[mode_name] = dict(job=job, res=res_t, wall=wall, step_ms=step_ms, kernel_ms=kms, ev=ev, tune=tune,
                                   table=job.p.table)
+        if probes_d is not None:
+            ph = probes_d.cpu().numpy().astype(np.float64) / (args.warmup + args.steps)
+            tot = ph.sum()
+            used = np.nonzero(ph)[0]
+            results[mode_name]["probes"] = {
+                "inserts_per_step": int(round(tot)),
+                "first_probe_frac": round(float(ph[1] / tot), 6) if tot else None,
+                "mean_probes": round(float((np.arange(ph.size) * ph)[1:].sum() / max(1.0, ph[1:].sum())), 4),
+                "max_probe_bucket": int(used.max()) if used.size else 0,
+                "emergency_without_probe": int(round(ph[0])),
+                "by_probe": {int(t): int(round(ph[t])) for t in used}}
+            print(f"[bench] {mode_name} probes: {results[mode_name]['probes']}", file=sys.stderr, flush=True)
         if clocks_d is not None:
             c = clocks_d.cpu().numpy()
             runs = args.warmup + args.steps
@@ -392,7 +415,7 @@ def main(argv=None):
     kname = {("batched", "lds"): "k_lds_persistent", ("plain", "lds"): "k_lds_stage",
              ("batched", "hbm"): "k_count_persistent", ("plain", "hbm"): "k_count_bin+k_compact"}[(head, head_table)]
     traffic = None
-    default_schedule = (not args.tune and args.load == 0.0 and args.pool == 0 and args.scale == 1.0
+    default_schedule = (not args.tune and args.load == 0.0 and args.pool == 0 and args.scale == 1.0 and args.block == 0
                         and not args.non_canonical and args.size_sample == 0)
     if default_schedule and "+" not in kname:
         traffic = measured_traffic(kname, w.name)
@@ -435,6 +458,8 @@ def main(argv=None):
             out[f"{m}_count_kernel_ms"] = r["kernel_ms"]
         if r.get("tune"):
             out[f"{m}_autotune"] = r["tune"]
+        if "probes" in r:
+            out[f"{m}_probes"] = r["probes"]
         if "stage_ms" in r:
             out[f"{m}_stage_busy_ms"] = r["stage_ms"]
             out[f"{m}_stage_items"] = r["stage_items"]
@@ -461,32 +486,52 @@ def main(argv=None):
 
 
 def run_serving(args):
-    """Poisson stream of independent jobs through the serving loop (arrival -> results on the host)."""
+    """Poisson stream of independent counting jobs through the serving loop
+    (arrival -> results on the host), at the jobs' stated sizes. The payloads
+    are the first D distinct seeded jobs of the stream, generated before
+    serving (the generator is not timed); the stream of N requests cycles
+    through them with its own Poisson arrival times, so host memory holds D
+    payloads, not N."""
     import concurrent.futures as cf
+    import dataclasses
 
     import synth
     from paper_1607_06618_amd import serve
 
     n = args.serving
+    d = max(1, min(n, args.serving_distinct))
     arrivals = synth.arrival_times(n)
 
     def make(j):
         w = synth.serving_job(j, scale=args.serving_scale)
         a, o = w.generate(threads=4)
-        return serve.make_request(j, a, o, w.k, w.m, w.n_bins, w.threshold, arrival=float(arrivals[j]))
+        return serve.make_request(j, a, o, w.k, w.m, w.n_bins, w.threshold, arrival=0.0)
 
     t = time.perf_counter()
     with cf.ThreadPoolExecutor(max_workers=4) as ex:
-        reqs = list(ex.map(make, range(n)))
+        payloads = list(ex.map(make, range(d)))
     gen_s = time.perf_counter() - t
+    reqs = [dataclasses.replace(payloads[j % d], job_id=j, arrival=float(arrivals[j])) for j in range(n)]
     import torch
     free, total = torch.cuda.mem_get_info()
+    # one warm-up pass over the distinct payloads (allocator, pinned pool, kernels), not timed
+    warm = serve.CountingServer(budget_bytes=int(free * 0.6), max_inflight=args.serving_inflight)
+    warm.serve([dataclasses.replace(r, arrival=0.0) for r in payloads[: min(d, 4)]], realtime=False)
     srv = serve.CountingServer(budget_bytes=int(free * 0.6), max_inflight=args.serving_inflight)
-    res = srv.serve(reqs, realtime=True)
+    srv.pool = warm.pool
+    res = []
+
+    def keep(r):   # the caller's side: take the timings, hand the pinned buffers back
+        r.release()
+        res.append(r)
+
+    srv.serve(reqs, realtime=True, on_result=keep)
     stats = serve.summarize(res, srv.makespan)
-    stats.update({"offered_jobs_per_s": synth.SERVING_RATE, "scale": args.serving_scale,
-                  "inflight": args.serving_inflight, "generation_s": round(gen_s, 1),
-                  "k_mix": sorted({r.k for r in reqs})})
+    stats["count_kernel_busy_frac"] = sum(r.count_kernel_ms for r in res) / 1000.0 / srv.makespan
+    stats.update({"offered_jobs_per_s": synth.SERVING_RATE, "requests": n, "distinct_payloads": d,
+                  "scale": args.serving_scale, "inflight": args.serving_inflight,
+                  "generation_s": round(gen_s, 1), "k_mix": sorted({r.k for r in payloads}),
+                  "mean_job_valid_windows": sum(r.n_valid for r in res) / max(1, len(res))})
     print(f"[bench] serving: {stats}", file=sys.stderr, flush=True)
     return stats
 

@@ -103,7 +103,11 @@ typedef struct {
                                 area)                                                             */
     uint32_t max_probes;     /* theta of Alg. 1: trials before the emergency path; 0 = default
                                 (8 buckets of 8 slots in HBM tables, 64 slots in LDS tables)     */
-    uint32_t block;          /* threads per workgroup for counting, 64..1024; 0 = default        */
+    uint32_t block;          /* threads per workgroup for counting, 64..1024 in steps of 64. HBM
+                                tables: 0 = 256. LDS tables, BATCHED: 512 runs two 512-thread
+                                workgroups per CU with 80 KB of LDS each (half-size tables whose
+                                stages overlap on the CU); any other value one 1024-thread
+                                workgroup per CU with 160 KB. LDS tables, PLAIN: always 1024     */
     uint32_t pool;           /* BATCHED: hash tables resident at once; 0 = chosen from budget    */
     uint64_t overflow_cap;   /* emergency-area capacity in keys; 0 = default                     */
     uint64_t superm_cap;     /* super-mer descriptor capacity; 0 = default estimate              */
@@ -124,7 +128,15 @@ typedef struct {
     const uint32_t* rank_table; /* order TABLE: device uint32 [4^m], the rank of each canonical m-mer
                                 code (distinct ranks below 0xFFFFFFFF; entries of other codes are
                                 never read). bin_map must be NULL with this order.               */
+    uint64_t* probe_hist;    /* optional device uint64[GERBIL_PROBE_HIST], zeroed by the caller; LDS
+                                tables, BATCHED: entry t (1 <= t < GERBIL_PROBE_HIST - 1) counts the
+                                k-mer occurrences whose insert ended at its t-th probe, the last
+                                entry those that needed more or took the emergency area, entry 0
+                                the occurrences sent to the emergency area without a probe (the
+                                probe statistic of Sec. 3.3.1). NULL = none (no cost)             */
 } gerbil_params;
+
+#define GERBIL_PROBE_HIST 32
 
 /* Output of gerbil_encode. All pointers point into the encode workspace. */
 typedef struct {
@@ -325,6 +337,8 @@ typedef struct {
     uint32_t candidates;     /* candidates timed (0 when the choice came from the cache) */
     uint32_t cached;         /* 1 if the choice came from the cache                      */
     float best_ms;           /* time of one gerbil_count with the choice                 */
+    uint32_t block;          /* chosen gerbil_params.block (LDS: 1024 or 512 threads per
+                                workgroup; HBM: 256, 512 or 1024)                            */
 } gerbil_tune_result;
 
 /* Workspace bytes that fit every candidate of gerbil_autotune for these
@@ -333,11 +347,12 @@ int32_t gerbil_autotune_workspace(const gerbil_bins* bins, const gerbil_params* 
                                   hipStream_t stream);
 
 /* Time gerbil_count on `bins` for each candidate of the grid (LDS tables:
- * load_factor 0.6/0.8/1.0/1.2 x pool 4/8/16; HBM tables: load_factor 0.4/0.6
- * x pool 8/32; p->table = LDS or HBM restricts the grid to that placement;
- * PLAIN mode has no pool) and write into *best a copy of *p with table,
- * load_factor and pool of the fastest candidate that finished without a
- * capacity error. Candidates whose workspace exceeds ws_bytes are skipped.
+ * load_factor 0.6/0.8/1.0/1.2 x pool 4/8/16 x block 1024/512; HBM tables:
+ * load_factor 0.4/0.6 x pool 8/32 x block 256/512/1024; p->table = LDS or
+ * HBM restricts the grid to that placement; PLAIN mode has no pool and LDS
+ * tables only block 1024) and write into *best a copy of *p with table,
+ * load_factor, pool and block of the fastest candidate that finished without
+ * a capacity error (one warm-up run, then one timed run per candidate). Candidates whose workspace exceeds ws_bytes are skipped.
  * keys/counts/cap serve as the output of the trial runs (their contents are
  * overwritten). The choice is cached per (device, ceil(k/32), m, n_bins,
  * mode, p->table, and the total, largest and median bin size in quarter

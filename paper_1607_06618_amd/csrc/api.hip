@@ -209,19 +209,33 @@ constexpr uint32_t kDefaultLdsTheta = 64;   // single-slot probes are cheap in L
 constexpr double kDefaultLdsFill = 0.8;     // k-mers per LDS slot (distinct keys are fewer)
 
 struct LdsSizing {
+    uint32_t block, max_sub;   // workgroup shape (LdsShape)
+    bool packed;               // packed table slots (lds_packed)
     uint32_t C, target, ranks_cap, Q, lag, sample;
     uint64_t sp_cap;
 };
+
+// Threads per LDS-path workgroup: two 512-thread workgroups per CU when the
+// batched schedule asks for blocks of 512, else one of 1024.
+uint32_t lds_block(const gerbil_params* p) {
+    return p->mode == GERBIL_BATCHED && p->block == 512 ? 512u : kLdsBlock;
+}
 
 constexpr uint32_t kDefaultSizeSample = 8;
 
 LdsSizing lds_sizing(const gerbil_params* p, uint64_t n_bytes) {
     LdsSizing z;
     const uint32_t W = words_for(p->k);
-    z.C = lds_table_slots(W);
+    z.block = lds_block(p);
+    z.max_sub = lds_max_sub_for(z.block);
+    z.packed = lds_packed(p->k);
+    z.C = lds_table_slots(W, z.block, z.packed);
     const double fill = p->load_factor > 0 ? p->load_factor : kDefaultLdsFill;
     z.target = std::max<uint32_t>(64, (uint32_t)((double)z.C * fill));
-    const uint64_t per_slice = (uint64_t)kLdsMaxSub * z.target;
+    // packed tables have more slots than one batch of keys fills: keep a sub-table to one batch
+    if (z.packed && !(p->load_factor > 0))
+        z.target = std::min<uint32_t>(z.target, (uint32_t)(0.95 * lds_table_batch((int)W) * z.block));
+    const uint64_t per_slice = (uint64_t)z.max_sub * z.target;
     z.ranks_cap = (uint32_t)std::min<uint64_t>(p->n_bins + n_bytes / per_slice + 1, 1u << 20);
     z.sp_cap = n_bytes / z.target + 2ull * z.ranks_cap + 1;
     if (p->mode == GERBIL_BATCHED) {
@@ -249,7 +263,7 @@ uint64_t lds_slot_keys(uint64_t max_kmers, const LdsSizing& z) {
     const double S = z.sample;
     double P = std::ceil(N / z.target);
     if (P < 1) P = 1;
-    if (P > kLdsMaxSub) P = kLdsMaxSub;
+    if (P > z.max_sub) P = z.max_sub;
     const double L = sample_seg_len(z.sample);
     const double bound = N + 4.0 * std::sqrt(S * L * N) + 4.0 * std::sqrt(S * L) * std::sqrt(P * (N + P * L)) + 33.0 * P;
     return (uint64_t)std::ceil(bound);
@@ -372,6 +386,8 @@ int32_t count_lds(const gerbil_bins* bins, const gerbil_params* p, void* ws, uin
     CountArgs a = count_args(p, bins, state, keys, counts, cap, L);
 
     LdsArgs l;
+    l.block = z.block;
+    l.max_sub = z.max_sub;
     l.n_bins = p->n_bins;
     l.ranks_cap = z.ranks_cap;
     l.n_ranks = LL.n_ranks;
@@ -395,8 +411,10 @@ int32_t count_lds(const gerbil_bins* bins, const gerbil_params* p, void* ws, uin
     l.target = z.target;
     l.sample = z.sample;
     l.table_slots = z.C;
+    l.packed = z.packed ? 1u : 0u;
     l.theta = p->max_probes ? p->max_probes : kDefaultLdsTheta;
     l.stage_clocks = p->stage_clocks;
+    l.probe_hist = batched ? p->probe_hist : nullptr;
     l.bin_off = bins->bin_off;
     l.bin_kmers = bins->bin_kmers;
     l.done = LL.done;
@@ -413,7 +431,9 @@ int32_t count_lds(const gerbil_bins* bins, const gerbil_params* p, void* ws, uin
     if (e != hipSuccess) return GERBIL_EDEVICE;
     if (batched) {
         if (p->timing_events) e = hipEventRecord(p->timing_events[0], stream);
-        if (e == hipSuccess) e = launch_lds_persistent(a, l, (uint32_t)device_cus(), stream);
+        // one 1024-thread workgroup per CU, or two of 512
+        const uint32_t grid = (uint32_t)device_cus() * (kLdsBlock / z.block);
+        if (e == hipSuccess) e = launch_lds_persistent(a, l, grid, stream);
         if (e == hipSuccess && p->timing_events) e = hipEventRecord(p->timing_events[1], stream);
     } else {
         uint32_t n_ranks = 0;
@@ -681,7 +701,9 @@ int32_t gerbil_count(const gerbil_bins* bins, const gerbil_params* p, void* ws, 
         q.Q = Q;
         q.lag = Q / 2;
         q.n_bins = n_bins;
-        q.ins_chunk = 256;
+        // threads per workgroup: 256, 512 or 1024 (other values take 256)
+        const uint32_t hb = p->block == 512 || p->block == 1024 ? p->block : 256u;
+        q.ins_chunk = hb;
         q.cmp_chunk = kCmpChunk;
         q.load = load;
         q.bin_off = bins->bin_off;
@@ -699,9 +721,9 @@ int32_t gerbil_count(const gerbil_bins* bins, const gerbil_params* p, void* ws, 
         q.superm_cap = bins->cap_superm;
         q.status = state->status;
         e = launch_plan(q, stream);
-        uint32_t grid = (uint32_t)device_cus() * persistent_blocks_per_cu(W, 256);
+        uint32_t grid = (uint32_t)device_cus() * persistent_blocks_per_cu(W, hb);
         if (e == hipSuccess && p->timing_events) e = hipEventRecord(p->timing_events[0], stream);
-        if (e == hipSuccess) e = launch_count_persistent(a, q, grid, 256, stream);
+        if (e == hipSuccess) e = launch_count_persistent(a, q, grid, hb, stream);
         if (e == hipSuccess && p->timing_events) e = hipEventRecord(p->timing_events[1], stream);
     } else {
         if (n_superm > bins->cap_superm) return GERBIL_OK;   // reported by gerbil_result as ECAPACITY

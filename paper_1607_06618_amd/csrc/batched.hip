@@ -122,9 +122,8 @@ hipError_t launch_plan(const PersistArgs& q, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int W>
-__global__ void __launch_bounds__(256) k_count_persistent(CountArgs a, PersistArgs q) {
-    constexpr uint32_t B = 256;
+template <int W, uint32_t B>
+__global__ void __launch_bounds__(B) k_count_persistent(CountArgs a, PersistArgs q) {
     __shared__ int64_t sstart[B];
     __shared__ uint32_t spre[B];
     __shared__ uint32_t wsum[17];
@@ -202,68 +201,85 @@ __global__ void __launch_bounds__(256) k_count_persistent(CountArgs a, PersistAr
         if (lh[b]) add_dev(&a.hist[b], (uint64_t)lh[b]);
 }
 
-template <int W>
+template <int W, uint32_t B>
 static hipError_t persistent_w(const CountArgs& a, const PersistArgs& q, uint32_t grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_count_persistent<W>, dim3(grid), dim3(256), 0, s, a, q);
+    hipLaunchKernelGGL((k_count_persistent<W, B>), dim3(grid), dim3(B), 0, s, a, q);
     return hipGetLastError();
 }
 
-hipError_t launch_count_persistent(const CountArgs& a, const PersistArgs& q, uint32_t grid, uint32_t block,
-                                   hipStream_t s) {
-    if (block != 256 || q.ins_chunk != 256) return hipErrorInvalidValue;
+template <uint32_t B>
+static hipError_t persistent_b(const CountArgs& a, const PersistArgs& q, uint32_t grid, hipStream_t s) {
     switch (a.W) {
-        case 1: return persistent_w<1>(a, q, grid, s);
-        case 2: return persistent_w<2>(a, q, grid, s);
-        case 3: return persistent_w<3>(a, q, grid, s);
-        case 4: return persistent_w<4>(a, q, grid, s);
-        case 5: return persistent_w<5>(a, q, grid, s);
-        case 6: return persistent_w<6>(a, q, grid, s);
-        case 7: return persistent_w<7>(a, q, grid, s);
-        case 8: return persistent_w<8>(a, q, grid, s);
-        case 9: return persistent_w<9>(a, q, grid, s);
-        case 10: return persistent_w<10>(a, q, grid, s);
-        case 11: return persistent_w<11>(a, q, grid, s);
-        case 12: return persistent_w<12>(a, q, grid, s);
-        case 13: return persistent_w<13>(a, q, grid, s);
-        case 14: return persistent_w<14>(a, q, grid, s);
-        case 15: return persistent_w<15>(a, q, grid, s);
+        case 1: return persistent_w<1, B>(a, q, grid, s);
+        case 2: return persistent_w<2, B>(a, q, grid, s);
+        case 3: return persistent_w<3, B>(a, q, grid, s);
+        case 4: return persistent_w<4, B>(a, q, grid, s);
+        case 5: return persistent_w<5, B>(a, q, grid, s);
+        case 6: return persistent_w<6, B>(a, q, grid, s);
+        case 7: return persistent_w<7, B>(a, q, grid, s);
+        case 8: return persistent_w<8, B>(a, q, grid, s);
+        case 9: return persistent_w<9, B>(a, q, grid, s);
+        case 10: return persistent_w<10, B>(a, q, grid, s);
+        case 11: return persistent_w<11, B>(a, q, grid, s);
+        case 12: return persistent_w<12, B>(a, q, grid, s);
+        case 13: return persistent_w<13, B>(a, q, grid, s);
+        case 14: return persistent_w<14, B>(a, q, grid, s);
+        case 15: return persistent_w<15, B>(a, q, grid, s);
     }
     return hipErrorInvalidValue;
 }
 
-template <int W>
-static uint32_t occupancy_w() {
+// One insert item is one descriptor per thread, so ins_chunk equals the block.
+hipError_t launch_count_persistent(const CountArgs& a, const PersistArgs& q, uint32_t grid, uint32_t block,
+                                   hipStream_t s) {
+    if (q.ins_chunk != block) return hipErrorInvalidValue;
+    switch (block) {
+        case 256: return persistent_b<256>(a, q, grid, s);
+        case 512: return persistent_b<512>(a, q, grid, s);
+        case 1024: return persistent_b<1024>(a, q, grid, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int W, uint32_t B>
+static uint32_t occupancy_wb() {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_count_persistent<W>, 256, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_count_persistent<W, B>, B, 0) != hipSuccess ||
         blocks < 1)
         blocks = 1;
     return (uint32_t)blocks;
 }
 
+template <int W>
+static uint32_t occupancy_w(uint32_t block) {
+    return block == 1024 ? occupancy_wb<W, 1024>() : block == 512 ? occupancy_wb<W, 512>() : occupancy_wb<W, 256>();
+}
+
 uint32_t persistent_blocks_per_cu(uint32_t W, uint32_t block) {
-    (void)block;
-    static std::atomic<uint32_t> cached[GERBIL_MAX_W + 1];   // zero-initialised; same value from any thread
+    // zero-initialised; the same value from any thread (per device of one kind)
+    static std::atomic<uint32_t> cached[3][GERBIL_MAX_W + 1];
     if (W < 1 || W > GERBIL_MAX_W) return 1;
-    if (const uint32_t c = cached[W].load(std::memory_order_relaxed)) return c;
+    const uint32_t bi = block == 1024 ? 2 : block == 512 ? 1 : 0;
+    if (const uint32_t c = cached[bi][W].load(std::memory_order_relaxed)) return c;
     uint32_t r = 1;
     switch (W) {
-        case 1: r = occupancy_w<1>(); break;
-        case 2: r = occupancy_w<2>(); break;
-        case 3: r = occupancy_w<3>(); break;
-        case 4: r = occupancy_w<4>(); break;
-        case 5: r = occupancy_w<5>(); break;
-        case 6: r = occupancy_w<6>(); break;
-        case 7: r = occupancy_w<7>(); break;
-        case 8: r = occupancy_w<8>(); break;
-        case 9: r = occupancy_w<9>(); break;
-        case 10: r = occupancy_w<10>(); break;
-        case 11: r = occupancy_w<11>(); break;
-        case 12: r = occupancy_w<12>(); break;
-        case 13: r = occupancy_w<13>(); break;
-        case 14: r = occupancy_w<14>(); break;
-        case 15: r = occupancy_w<15>(); break;
+        case 1: r = occupancy_w<1>(block); break;
+        case 2: r = occupancy_w<2>(block); break;
+        case 3: r = occupancy_w<3>(block); break;
+        case 4: r = occupancy_w<4>(block); break;
+        case 5: r = occupancy_w<5>(block); break;
+        case 6: r = occupancy_w<6>(block); break;
+        case 7: r = occupancy_w<7>(block); break;
+        case 8: r = occupancy_w<8>(block); break;
+        case 9: r = occupancy_w<9>(block); break;
+        case 10: r = occupancy_w<10>(block); break;
+        case 11: r = occupancy_w<11>(block); break;
+        case 12: r = occupancy_w<12>(block); break;
+        case 13: r = occupancy_w<13>(block); break;
+        case 14: r = occupancy_w<14>(block); break;
+        case 15: r = occupancy_w<15>(block); break;
     }
-    cached[W].store(r, std::memory_order_relaxed);
+    cached[bi][W].store(r, std::memory_order_relaxed);
     return r;
 }
 

@@ -134,9 +134,23 @@ hipError_t launch_count_persistent(const CountArgs& a, const PersistArgs& q, uin
 uint32_t persistent_blocks_per_cu(uint32_t W, uint32_t block);
 
 // LDS sub-table path. A rank is one hash slice of a bin (bins too large for
-// kLdsMaxSub sub-tables are cut into slices by the high hash bits); a rank
-// has P sub-tables, each counted by one workgroup in LDS.
-constexpr uint32_t kLdsBlock = 1024;
+// max_sub sub-tables are cut into slices by the high hash bits); a rank has P
+// sub-tables, each counted by one workgroup in LDS.
+//
+// Two workgroup shapes share the CU's 160 KB of LDS: one workgroup of 1024
+// threads per CU with all of it, or two of 512 threads with half each (their
+// stages then overlap on the CU; tables hold half as many keys). The per-bin
+// schedule always uses the first.
+constexpr uint32_t kLdsBlock = 1024;   // threads of the 1024-thread shape (and of the per-bin schedule)
+template <uint32_t B>
+struct LdsShape {
+    static_assert(B == 1024 || B == 512, "LDS workgroups have 512 or 1024 threads");
+    static constexpr uint32_t bytes = (160u * 1024u) / (1024u / B);   // dynamic LDS per workgroup
+    // sub-tables per rank: bounded by the three per-sub-table arrays of the scatter stage
+    static constexpr uint32_t max_sub = B == 1024 ? 4096u : 1536u;
+};
+inline uint32_t lds_bytes_for(uint32_t B) { return B == 512 ? LdsShape<512>::bytes : LdsShape<1024>::bytes; }
+inline uint32_t lds_max_sub_for(uint32_t B) { return B == 512 ? LdsShape<512>::max_sub : LdsShape<1024>::max_sub; }
 // Bytes that hold the last word of a key: 2 bits per base of its k - 32(W-1) bases.
 inline uint32_t tail_bytes_for(uint32_t k) {
     const uint32_t W = (k + 31) / 32, r = k - 32 * (W - 1);
@@ -157,15 +171,26 @@ __host__ __device__ inline uint64_t run_capacity(uint64_t c, uint32_t S) {
 inline uint64_t slot_words_for(uint64_t slot_keys, uint32_t k) {
     const uint32_t W = (k + 31) / 32;
     return slot_keys * (W - 1) + (slot_keys * tail_bytes_for(k) + 7) / 8;
-}            // threads per workgroup (one workgroup per CU)
-constexpr uint32_t kLdsBytes = 160 * 1024;      // dynamic LDS per workgroup
-constexpr uint32_t kLdsMaxSub = 4096;           // sub-tables per rank (LDS of the scatter stage)
+}
 constexpr uint32_t kLdsReserved = 2048;         // LDS kept for the histogram and scalars
+constexpr uint32_t kProbeHist = 32;             // probe-count buckets (GERBIL_PROBE_HIST)
+constexpr uint32_t kProbeHistAt = 1536;         // their LDS copy inside the reserved region
 // Slots of an LDS table: the largest prime that fits, so that double hashing
 // has a full period.
 constexpr uint32_t kLdsTableScratch = 256;      // scan scratch of the table stage after its slots
-inline uint32_t lds_table_slots(uint32_t W) {
-    uint32_t c = (kLdsBytes - kLdsReserved - kLdsTableScratch) / (8 * W + 4);
+// Keys an LDS-table thread loads per batch (registers bound it); a sub-table
+// gets at most 0.95 of a batch, so it is loaded in one.
+__host__ __device__ constexpr int lds_table_batch(int W) {
+    return W == 1 ? 12 : W == 2 ? 7 : W == 3 ? 5 : W == 4 ? 4 : W <= 7 ? 3 : 2;
+}
+// Packed slots hold a key's last word (at most 16 bases, 32 bits) in the high
+// half of the counter's 64-bit word: 8W bytes a slot instead of 8W + 4.
+inline bool lds_packed(uint32_t k) {
+    const uint32_t W = (k + 31) / 32;
+    return W >= 2 && k - 32 * (W - 1) <= 16;
+}
+inline uint32_t lds_table_slots(uint32_t W, uint32_t B, bool packed) {
+    uint32_t c = (lds_bytes_for(B) - kLdsReserved - kLdsTableScratch) / (packed ? 8 * W : 8 * W + 4);
     for (;; c--) {
         bool prime = c > 2;
         for (uint32_t d = 2; prime && d * d <= c; d++) prime = c % d != 0;
@@ -174,13 +199,15 @@ inline uint32_t lds_table_slots(uint32_t W) {
 }
 
 struct LdsArgs {
+    uint32_t block;           // threads per workgroup: 1024 or 512 (LdsShape)
+    uint32_t max_sub;         // LdsShape<block>::max_sub
     uint32_t n_bins, ranks_cap;
     uint32_t* n_ranks;        // scalar (plan output)
     uint32_t* rank_bin;       // [ranks_cap]
     uint32_t* rank_slice;
     uint32_t* rank_nslice;
     uint32_t* rank_nsub;      // P (0 for an empty bin)
-    uint32_t* rank_nchunk;    // descriptor chunks of kLdsBlock
+    uint32_t* rank_nchunk;    // descriptor chunks of `block` descriptors
     uint64_t* rank_spbase;    // first sub-table of the rank
     uint64_t* rank_keys;      // keys of the rank (scan output)
     uint64_t sp_cap;
@@ -198,8 +225,10 @@ struct LdsArgs {
     uint32_t target;          // keys per sub-table
     uint32_t sample;          // sub-table runs sized from every sample-th super-mer (1 = all)
     uint32_t table_slots;     // LDS slots per sub-table
+    uint32_t packed;          // 1: packed slots (the last key word shares a 64-bit word with the counter)
     uint32_t theta;           // probes per key before the emergency area
     uint64_t* stage_clocks;   // optional [8]: busy wall-clock ticks per stage, then items per stage
+    uint64_t* probe_hist;     // optional [kProbeHist]: inserts by the probe that settled them
     const uint64_t* bin_off;
     const uint64_t* bin_kmers;
     uint32_t* done;           // [4 * ranks_cap] finished items per (rank, stage)

@@ -32,7 +32,7 @@ __device__ __forceinline__ uint32_t sub_of(uint64_t h, uint32_t P) { return fast
 
 // ----------------------------------------------------------------- plan
 // One workgroup. Ranks follow the bins in LPT order (largest first); a bin
-// with more k-mers than kLdsMaxSub sub-tables of `target` keys is cut into
+// with more k-mers than max_sub sub-tables of `target` keys is cut into
 // V slices. Queue segment 4*tick + stage holds stage `stage` of rank
 // tick - lag[stage], lag = {0, 1, 2, 2 + L}: every dependency of an item is
 // in an earlier segment.
@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(1024) k_lds_plan(LdsArgs l) {
         }
     }
     const bool overfull = *l.n_superm > l.superm_cap;
-    const uint64_t per_slice = (uint64_t)kLdsMaxSub * l.target;
+    const uint64_t per_slice = (uint64_t)l.max_sub * l.target;
     // 1. slices per bin (in LPT order) and their prefix -> first rank of each bin
     auto slices = [&](uint32_t i) -> uint64_t {
         uint64_t km = skey[i];
@@ -99,14 +99,14 @@ __global__ void __launch_bounds__(1024) k_lds_plan(LdsArgs l) {
             uint64_t kest = (skey[i] + V - 1) / V;
             uint64_t P = (kest + l.target - 1) / l.target;
             if (P < 1) P = 1;
-            if (P > kLdsMaxSub) P = kLdsMaxSub;
+            if (P > l.max_sub) P = l.max_sub;
             bool empty = nd == 0 || overfull;
             for (uint64_t v = 0; v < V; v++, r++) {
                 l.rank_bin[r] = b;
                 l.rank_slice[r] = (uint32_t)v;
                 l.rank_nslice[r] = (uint32_t)V;
                 l.rank_nsub[r] = empty ? 0u : (uint32_t)P;
-                l.rank_nchunk[r] = empty ? 0u : (uint32_t)((nd + kLdsBlock - 1) / kLdsBlock);
+                l.rank_nchunk[r] = empty ? 0u : (uint32_t)((nd + l.block - 1) / l.block);
             }
         }
     }
@@ -207,12 +207,14 @@ hipError_t launch_lds_plan(const LdsArgs& l, hipStream_t s) {
 // ---------------------------------------------------------- LDS layout
 struct Lds {
     uint32_t* hist;     // [kLdsHist] count-of-counts, flushed at the end of the kernel
+    uint32_t* probes;   // [kProbeHist] inserts by settling probe (only with LdsArgs::probe_hist)
     uint32_t* flag;     // one word for block-wide votes (last word of the reserved region)
     uint8_t* u;         // union region, carved per stage
 };
 __device__ __forceinline__ Lds lds_carve(uint8_t* base) {
     Lds x;
     x.hist = (uint32_t*)base;
+    x.probes = (uint32_t*)(base + kProbeHistAt);
     x.flag = (uint32_t*)(base + kLdsReserved - 4);
     x.u = base + kLdsReserved;
     return x;
@@ -220,19 +222,20 @@ __device__ __forceinline__ Lds lds_carve(uint8_t* base) {
 
 // Descriptor chunk `chunk` of bin b, one descriptor per thread, with every
 // super-mer cut into segments of at most L k-mers: sdesc[d] is descriptor d,
-// sgpre[d] the first segment of d (sgpre[kLdsBlock] = number of segments).
+// sgpre[d] the first segment of d (sgpre[B] = number of segments).
+template <uint32_t B>
 __device__ __forceinline__ uint32_t load_chunk_seg(const CountArgs& a, const LdsArgs& l, uint32_t b, uint32_t chunk,
                                                    uint32_t L, uint64_t* sdesc, uint32_t* sgpre, uint32_t* wsum) {
     const uint32_t tid = threadIdx.x;
     const uint64_t d_end = l.bin_off[b + 1];
-    const uint64_t i = l.bin_off[b] + (uint64_t)chunk * kLdsBlock + tid;
+    const uint64_t i = l.bin_off[b] + (uint64_t)chunk * B + tid;
     const uint64_t d = i < d_end ? a.desc[i] : 0ull;
     const uint32_t n = (uint32_t)(d & 0xFFFFFFu);
     uint32_t total;
     const uint32_t pre = block_excl_scan((n + L - 1) / L, wsum, total);
     sdesc[tid] = d;
     sgpre[tid] = pre;
-    if (tid == 0) sgpre[kLdsBlock] = total;
+    if (tid == 0) sgpre[B] = total;
     __syncthreads();
     return total;
 }
@@ -266,10 +269,10 @@ struct SegRaw {
     bool ok;
 };
 
-template <int W>
+template <int W, uint32_t B>
 __device__ __forceinline__ void seg_fetch(const CountArgs& a, const uint64_t* sdesc, const uint32_t* sgpre, uint32_t sg,
                                           uint32_t L, SegRaw<W>& r) {
-    uint32_t lo = 0, hi = kLdsBlock;   // last descriptor whose first segment is <= sg
+    uint32_t lo = 0, hi = B;   // last descriptor whose first segment is <= sg
     while (hi - lo > 1) {
         uint32_t mid = (lo + hi) >> 1;
         if (sgpre[mid] <= sg) lo = mid; else hi = mid;
@@ -331,17 +334,17 @@ __device__ __forceinline__ void seg_build(const SegRaw<W>& r, uint32_t k, Segmen
 // Open a segment at once. Short keys go through seg_fetch/seg_build (W + 2
 // loads); longer keys read each 32-base window directly, which keeps fewer
 // words live at a time.
-template <int W>
+template <int W, uint32_t B>
 __device__ __forceinline__ void seg_open(const CountArgs& a, const uint64_t* sdesc, const uint32_t* sgpre, uint32_t sg,
                                          uint32_t L, Segment<W>& g) {
     if (W <= 3) {
         SegRaw<W> r;
-        seg_fetch<W>(a, sdesc, sgpre, sg, L, r);
+        seg_fetch<W, B>(a, sdesc, sgpre, sg, L, r);
         if (r.ok) seg_build<W>(r, a.k, g);
         else g.ok = false;
         return;
     }
-    uint32_t lo = 0, hi = kLdsBlock;   // last descriptor whose first segment is <= sg
+    uint32_t lo = 0, hi = B;   // last descriptor whose first segment is <= sg
     while (hi - lo > 1) {
         uint32_t mid = (lo + hi) >> 1;
         if (sgpre[mid] <= sg) lo = mid; else hi = mid;
@@ -443,8 +446,9 @@ __device__ __forceinline__ bool block_any(bool v, uint32_t* flag) {
 }
 
 // Exclusive prefix of cnt[0..n) into pre[0..n) by the whole block; returns the total.
+template <uint32_t B>
 __device__ __forceinline__ uint32_t block_scan_array(const uint32_t* cnt, uint32_t* pre, uint32_t n, uint32_t* wsum) {
-    const uint32_t per = (n + kLdsBlock - 1) / kLdsBlock;
+    const uint32_t per = (n + B - 1) / B;
     const uint32_t j0 = threadIdx.x * per;
     uint32_t sum = 0;
     for (uint32_t e = 0; e < per; e++)
@@ -465,7 +469,8 @@ template <int W>
 struct ScatterRound { static constexpr int R = W == 1 ? 8 : W == 2 ? 5 : W == 3 ? 4 : W == 4 ? 3 : W == 5 ? 2 : 1; };
 
 // LDS of the chunk stages: descriptors, segment prefixes and scan scratch.
-constexpr uint32_t kChunkHeader = 8 * kLdsBlock + 4 * (kLdsBlock + 4) + 4 * 32;
+template <uint32_t B>
+constexpr uint32_t chunk_header() { return 8 * B + 4 * (B + 4) + 4 * 32; }
 
 struct ChunkLds {
     uint64_t* sdesc;
@@ -473,31 +478,33 @@ struct ChunkLds {
     uint32_t* wsum;
     uint8_t* rest;
 };
+template <uint32_t B>
 __device__ __forceinline__ ChunkLds chunk_lds(const Lds& s) {
     ChunkLds c;
     c.sdesc = (uint64_t*)s.u;
-    c.sgpre = (uint32_t*)(s.u + 8 * kLdsBlock);
-    c.wsum = c.sgpre + kLdsBlock + 4;
+    c.sgpre = (uint32_t*)(s.u + 8 * B);
+    c.wsum = c.sgpre + B + 4;
     c.rest = (uint8_t*)(c.wsum + 32);
     return c;
 }
 
 // Stage A: keys of this slice per sub-table. One segment of up to 32 k-mers
 // per thread and round, so all lanes read their first k-mer together.
-template <int W>
+template <int W, uint32_t B>
 __device__ void stage_count(const CountArgs& a, const LdsArgs& l, const Lds& s, uint32_t r, uint32_t chunk) {
     const uint32_t tid = threadIdx.x;
     const uint32_t b = l.rank_bin[r], v = l.rank_slice[r], V = l.rank_nslice[r], P = l.rank_nsub[r];
-    const ChunkLds c = chunk_lds(s);
-    static_assert(kChunkHeader + 4 * kLdsMaxSub <= kLdsBytes - kLdsReserved, "count stage exceeds the LDS budget");
+    const ChunkLds c = chunk_lds<B>(s);
+    static_assert(chunk_header<B>() + 4 * LdsShape<B>::max_sub <= LdsShape<B>::bytes - kLdsReserved,
+                  "count stage exceeds the LDS budget");
     uint32_t* hist = (uint32_t*)c.rest;
-    for (uint32_t j = tid; j < P; j += kLdsBlock) hist[j] = 0;
+    for (uint32_t j = tid; j < P; j += B) hist[j] = 0;
     // with sampling, segments are short and only every l.sample-th one is walked
     const uint32_t smp = l.sample > 1 ? l.sample : 1u, L = smp > 1 ? sample_seg_len(smp) : kSegMax;
-    const uint32_t S = load_chunk_seg(a, l, b, chunk, L, c.sdesc, c.sgpre, c.wsum);
-    for (uint32_t sg = tid * smp; sg < S; sg += kLdsBlock * smp) {
+    const uint32_t S = load_chunk_seg<B>(a, l, b, chunk, L, c.sdesc, c.sgpre, c.wsum);
+    for (uint32_t sg = tid * smp; sg < S; sg += B * smp) {
         Segment<W> g;
-        seg_open<W>(a, c.sdesc, c.sgpre, sg, L, g);
+        seg_open<W, B>(a, c.sdesc, c.sgpre, sg, L, g);
         if (!g.ok) continue;
         for (uint32_t j = 0; j < g.len; j++) {
             if (j) seg_step<W>(a.k, g);
@@ -510,16 +517,17 @@ __device__ void stage_count(const CountArgs& a, const LdsArgs& l, const Lds& s, 
     }
     __syncthreads();
     const uint64_t sb = l.rank_spbase[r];
-    for (uint32_t j = tid; j < P; j += kLdsBlock)
+    for (uint32_t j = tid; j < P; j += B)
         if (hist[j]) add_dev(&l.sp_cnt[sb + j], hist[j]);
 }
 
 // Stage S: sub-table runs of the rank (one workgroup).
+template <uint32_t B>
 __device__ void stage_scan(const CountArgs& a, const LdsArgs& l, const Lds& s, uint32_t r) {
     const uint32_t tid = threadIdx.x, P = l.rank_nsub[r];
     const uint64_t sb = l.rank_spbase[r];
     uint64_t* part = (uint64_t*)s.u;
-    const uint32_t per = (P + kLdsBlock - 1) / kLdsBlock;
+    const uint32_t per = (P + B - 1) / B;
     uint64_t sum = 0;
     // sampled counts -> run capacities (sp_cnt then holds the capacity)
     for (uint32_t e = 0; e < per; e++) {
@@ -533,7 +541,7 @@ __device__ void stage_scan(const CountArgs& a, const LdsArgs& l, const Lds& s, u
     }
     part[tid] = sum;
     __syncthreads();
-    for (uint32_t off = 1; off < kLdsBlock; off <<= 1) {
+    for (uint32_t off = 1; off < B; off <<= 1) {
         uint64_t y = tid >= off ? part[tid - off] : 0ull;
         __syncthreads();
         part[tid] += y;
@@ -549,8 +557,8 @@ __device__ void stage_scan(const CountArgs& a, const LdsArgs& l, const Lds& s, u
         }
     }
     if (tid == 0) {
-        st_dev(&l.rank_keys[r], part[kLdsBlock - 1]);
-        if (part[kLdsBlock - 1] > l.slot_keys) set_status(a.status, ST_POOL);
+        st_dev(&l.rank_keys[r], part[B - 1]);
+        if (part[B - 1] > l.slot_keys) set_status(a.status, ST_POOL);
     }
 }
 
@@ -558,7 +566,7 @@ __device__ void stage_scan(const CountArgs& a, const LdsArgs& l, const Lds& s, u
 // every thread takes one segment of up to R k-mers (keys held in registers);
 // the round's keys are grouped by sub-table in LDS, one global reservation is
 // made per sub-table, and each run is written as consecutive words.
-template <int W>
+template <int W, uint32_t B>
 __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s, uint32_t r, uint32_t chunk) {
     constexpr int R = ScatterRound<W>::R;
     const uint32_t tid = threadIdx.x;
@@ -566,16 +574,16 @@ __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s
     const uint64_t sb = l.rank_spbase[r];
     uint64_t* slot = l.keys + (uint64_t)(r % l.Q) * l.slot_words;
     uint8_t* tail = (uint8_t*)(slot + (uint64_t)(W - 1) * l.slot_keys);
-    const ChunkLds c = chunk_lds(s);
-    static_assert(kChunkHeader + 3 * 4 * kLdsMaxSub + (uint64_t)R * 8 * W * kLdsBlock <= kLdsBytes - kLdsReserved,
+    const ChunkLds c = chunk_lds<B>(s);
+    static_assert(chunk_header<B>() + 3 * 4 * LdsShape<B>::max_sub + (uint64_t)R * 8 * W * B <= LdsShape<B>::bytes - kLdsReserved,
                   "scatter stage exceeds the LDS budget");
     uint32_t* cnt = (uint32_t*)c.rest;
-    uint32_t* lp = cnt + kLdsMaxSub;
-    uint32_t* dst = lp + kLdsMaxSub;   // run start of this round, relative to the key slot
-    uint64_t* buf = (uint64_t*)(dst + kLdsMaxSub);
-    for (uint32_t j = tid; j < P; j += kLdsBlock) cnt[j] = 0;
-    const uint32_t S = load_chunk_seg(a, l, b, chunk, R, c.sdesc, c.sgpre, c.wsum);
-    const uint32_t rounds = (S + kLdsBlock - 1) / kLdsBlock;
+    uint32_t* lp = cnt + LdsShape<B>::max_sub;
+    uint32_t* dst = lp + LdsShape<B>::max_sub;   // run start of this round, relative to the key slot
+    uint64_t* buf = (uint64_t*)(dst + LdsShape<B>::max_sub);
+    for (uint32_t j = tid; j < P; j += B) cnt[j] = 0;
+    const uint32_t S = load_chunk_seg<B>(a, l, b, chunk, R, c.sdesc, c.sgpre, c.wsum);
+    const uint32_t rounds = (S + B - 1) / B;
     // the segment of the next round is opened (its packed words requested)
     // while the current round is written out
     // For short keys the next round's words are fetched while this round is
@@ -583,20 +591,20 @@ __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s
     constexpr bool kAhead = W <= 3;
     SegRaw<W> raw;
     raw.ok = false;
-    if (kAhead && tid < S) seg_fetch<W>(a, c.sdesc, c.sgpre, tid, R, raw);
+    if (kAhead && tid < S) seg_fetch<W, B>(a, c.sdesc, c.sgpre, tid, R, raw);
     for (uint32_t round = 0; round < rounds; round++) {
         uint64_t key[R][W];
         uint32_t sp[R], rk[R];
 #pragma unroll
         for (int e = 0; e < R; e++) sp[e] = kNone;
-        const uint32_t sg = round * kLdsBlock + tid;
+        const uint32_t sg = round * B + tid;
         if (sg < S) {
             Segment<W> g;
             g.ok = false;
             if (kAhead) {
                 if (raw.ok) seg_build<W>(raw, a.k, g);
             } else {
-                seg_open<W>(a, c.sdesc, c.sgpre, sg, R, g);
+                seg_open<W, B>(a, c.sdesc, c.sgpre, sg, R, g);
             }
             if (g.ok) {
 #pragma unroll
@@ -614,9 +622,9 @@ __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s
             }
         }
         __syncthreads();
-        const uint32_t T = block_scan_array(cnt, lp, P, c.wsum);
+        const uint32_t T = block_scan_array<B>(cnt, lp, P, c.wsum);
         __syncthreads();   // every lp[] written (and every cnt[] read) before keys are placed or counts reset
-        for (uint32_t j = tid; j < P; j += kLdsBlock) {
+        for (uint32_t j = tid; j < P; j += B) {
             const uint32_t n = cnt[j];
             if (n) {
                 const uint32_t gsub = add_dev(&l.sp_cur[sb + j], n);
@@ -634,13 +642,13 @@ __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s
         }
         if (kAhead) {
             raw.ok = false;
-            if (sg + kLdsBlock < S) seg_fetch<W>(a, c.sdesc, c.sgpre, sg + kLdsBlock, R, raw);
+            if (sg + B < S) seg_fetch<W, B>(a, c.sdesc, c.sgpre, sg + B, R, raw);
         }
         __syncthreads();
         // stores only: nothing in this loop waits for memory (a returning
         // atomic here would make every iteration wait for all earlier stores)
         uint32_t spilled = 0;
-        for (uint32_t i = tid; i < T; i += kLdsBlock) {
+        for (uint32_t i = tid; i < T; i += B) {
             uint32_t lo = 0, hi = P;   // last sub-table whose run starts at or before i
             while (hi - lo > 1) {
                 uint32_t mid = (lo + hi) >> 1;
@@ -665,7 +673,7 @@ __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s
         }
         // keys past the end of their run (runs are sized from a sample): emergency area
         if (block_any(spilled != 0, s.flag)) {
-            for (uint32_t i = tid; i < T; i += kLdsBlock) {
+            for (uint32_t i = tid; i < T; i += B) {
                 uint32_t lo = 0, hi = P;
                 while (hi - lo > 1) {
                     uint32_t mid = (lo + hi) >> 1;
@@ -676,10 +684,11 @@ __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s
 #pragma unroll
                 for (int w = 0; w < W; w++) key[w] = buf[(uint64_t)i * W + w];
                 overflow_push<W>(a, key);
+                if (l.probe_hist) atomicAdd(&s.probes[0], 1u);
             }
         }
         __syncthreads();
-        for (uint32_t j = tid; j < P; j += kLdsBlock) cnt[j] = 0;
+        for (uint32_t j = tid; j < P; j += B) cnt[j] = 0;
         __syncthreads();   // counts cleared before the next round adds to them
     }
 }
@@ -697,9 +706,16 @@ __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s
 // another claimer, is probed again in the next iteration. Keys whose theta
 // probes fail, and keys whose first word is the empty-slot marker (an all-T
 // word, never stored), go to the emergency area.
-template <int K, int W>
+//
+// Slot layouts (PK): unpacked, probe words w0[C], the other words rest[(W-1) C]
+// and 32-bit counters cnt[C]; packed (W >= 2 and a last word of at most 16
+// bases), w0[C], the middle words rest[(W-2) C] and one 64-bit word per slot
+// holding the last key word in its high half and the counter in its low half
+// (tc[C]): 8W bytes a slot instead of 8W + 4, and one read fewer per probe.
+template <int K, int W, bool PK>
 __device__ __forceinline__ void lds_insert_all(const CountArgs& a, uint64_t* w0, uint64_t* rest, uint32_t* cnt,
-                                               uint32_t C, uint32_t theta, uint64_t (&key)[K][W], uint32_t n) {
+                                               uint64_t* tc, uint32_t C, uint32_t theta, uint64_t (&key)[K][W],
+                                               uint32_t n, uint32_t* probes) {
     // C is prime and 1 <= step < C: double hashing visits theta distinct slots.
     // The sub-table is chosen by the top bits of h's low half and the slice by
     // the top bits of its high half, so the slot and the step take bits 0-19
@@ -711,24 +727,33 @@ __device__ __forceinline__ void lds_insert_all(const CountArgs& a, uint64_t* w0,
         st[e] = 1u + fastrange32((uint32_t)((h >> 32) << 12), C - 1);
         sl[e] = fastrange32((uint32_t)(h << 12), C);
     }
-    constexpr int RW = W > 1 ? W - 1 : 1;
+    constexpr int RW = PK ? (W > 2 ? W - 2 : 1) : (W > 1 ? W - 1 : 1);   // words read after the counter
+    constexpr int NR = PK ? W - 2 : W - 1;                                 // of which in use
     uint32_t t = 0, spins = 0;
     while (__ballot(n > 0) != 0ull) {
         if (n > 0) {
             bool settled = false;
+            uint32_t pb = 0;   // probe bucket of the key when it settles (probe statistic)
             if (key[0][0] == GERBIL_EMPTY) {
                 overflow_push<W>(a, key[0]);
                 settled = true;
             } else {
+                pb = t + 1 < kProbeHist - 1 ? t + 1 : kProbeHist - 1;
                 const uint32_t s = sl[0];
                 const uint64_t cur = __hip_atomic_load(w0 + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                uint32_t c = 1;
+                bool published = true;
+                uint64_t ctc = 0;
                 uint64_t rw[RW];
                 if (W > 1) {
-                    c = __hip_atomic_load(cnt + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if (PK) {
+                        ctc = __hip_atomic_load(tc + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        published = ctc != 0;
+                    } else {
+                        published = __hip_atomic_load(cnt + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0;
+                    }
                     asm volatile("" ::: "memory");   // the other words are read after the counter
 #pragma unroll
-                    for (int i = 0; i + 1 < W; i++)
+                    for (int i = 0; i < NR; i++)
                         rw[i] = __hip_atomic_load(rest + (uint32_t)i * C + s, __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
@@ -739,22 +764,36 @@ __device__ __forceinline__ void lds_insert_all(const CountArgs& a, uint64_t* w0,
                                                          __HIP_MEMORY_SCOPE_WORKGROUP);
                     if (exp == GERBIL_EMPTY) {
 #pragma unroll
-                        for (int i = 1; i < W; i++) rest[(uint32_t)(i - 1) * C + s] = key[0][i];
-                        if (W > 1) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                        __hip_atomic_fetch_add(cnt + s, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        for (int i = 0; i < NR; i++) rest[(uint32_t)i * C + s] = key[0][i + 1];
+                        if (PK) {
+                            // the last word and a count of one, published together
+                            if (NR > 0) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                            __hip_atomic_store(tc + s, (key[0][W - 1] << 32) | 1ull, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                        } else {
+                            if (W > 1) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                            __hip_atomic_fetch_add(cnt + s, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        }
                         settled = true;
                     } else {
                         again = true;
                     }
                 } else if (cur == key[0][0]) {
-                    bool eq = c != 0;
+                    bool eq = published;
 #pragma unroll
-                    for (int i = 0; i + 1 < W; i++) eq &= rw[i] == key[0][i + 1];
+                    for (int i = 0; i < NR; i++) eq &= rw[i] == key[0][i + 1];
+                    if (PK) eq &= (ctc >> 32) == key[0][W - 1];
                     if (eq) {
-                        // a run holds fewer than 2^32 keys, so a count cannot wrap
-                        __hip_atomic_fetch_add(cnt + s, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        // a run holds fewer than 2^32 keys, so a count cannot wrap; a packed
+                        // slot's counter is the low 32-bit half of its word (a 32-bit add
+                        // costs half of a 64-bit one in LDS)
+                        if (PK)
+                            __hip_atomic_fetch_add((uint32_t*)(tc + s), 1u, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+                        else
+                            __hip_atomic_fetch_add(cnt + s, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                         settled = true;
-                    } else if (c == 0) {
+                    } else if (!published) {
                         again = true;
                         if (++spins > kLdsSpin) {
                             set_status(a.status, ST_SPIN);
@@ -766,6 +805,7 @@ __device__ __forceinline__ void lds_insert_all(const CountArgs& a, uint64_t* w0,
                     if (++t >= theta) {
                         overflow_push<W>(a, key[0]);
                         settled = true;
+                        pb = kProbeHist - 1;
                     } else {
                         const uint32_t x = s + st[0];
                         sl[0] = x >= C ? x - C : x;
@@ -773,6 +813,7 @@ __device__ __forceinline__ void lds_insert_all(const CountArgs& a, uint64_t* w0,
                 }
             }
             if (settled) {
+                if (probes) atomicAdd(&probes[pb], 1u);
                 n--;
                 t = 0;
                 spins = 0;
@@ -791,22 +832,24 @@ __device__ __forceinline__ void lds_insert_all(const CountArgs& a, uint64_t* w0,
 // Keys loaded per thread before they are inserted (independent loads in
 // flight): enough that a sub-table filled to its default target (0.8 of the
 // slots) is loaded in one batch.
-template <int W>
+template <int W, bool PK>
 struct TableBatch {
-    static constexpr int K = W == 1 ? 12 : W == 2 ? 7 : W == 3 ? 5 : W == 4 ? 4 : W <= 7 ? 3 : 2;
+    static constexpr int K = lds_table_batch(W);
 };
 
 // Stage D: count one sub-table in LDS, then dump it.
-template <int W>
+template <int W, uint32_t B, bool PK>
 __device__ void stage_table(const CountArgs& a, const LdsArgs& l, const Lds& s, uint32_t r, uint32_t j,
                             uint32_t& wmax) {
-    constexpr int K = TableBatch<W>::K;
+    constexpr int K = TableBatch<W, PK>::K;
     const uint32_t tid = threadIdx.x;
     const uint32_t C = l.table_slots;
     uint64_t* w0 = (uint64_t*)s.u;
     uint64_t* rest = w0 + C;
+    // packed: tc[C] after the middle words; unpacked: cnt[C] after the other words
+    uint64_t* tc = rest + (uint64_t)(W >= 2 ? W - 2 : 0) * C;
     uint32_t* cnt = (uint32_t*)(rest + (uint64_t)(W - 1) * C);
-    uint32_t* wsum = cnt + C + 1;
+    uint32_t* wsum = PK ? (uint32_t*)(tc + C) + 1 : cnt + C + 1;
     uint64_t* s_base = (uint64_t*)(((uintptr_t)(wsum + 32) + 7) & ~(uintptr_t)7);
     const uint64_t sb = l.rank_spbase[r];
     const uint32_t n_put = ld_dev(&l.sp_cur[sb + j]), n_cap = ld_dev(&l.sp_cnt[sb + j]);
@@ -821,19 +864,21 @@ __device__ void stage_table(const CountArgs& a, const LdsArgs& l, const Lds& s, 
     // keys past its end are then already in the emergency area, so every key
     // of this sub-table goes there too and each key is counted in one place.
     const bool spill = n_put > n_cap;
-    for (uint32_t i = tid; i < C; i += kLdsBlock) {
+    for (uint32_t i = tid; i < C; i += B) {
         w0[i] = GERBIL_EMPTY;
-        cnt[i] = 0;
+        if (PK) tc[i] = 0; else cnt[i] = 0;
     }
     __syncthreads();
-    for (uint64_t base = 0; base < lim; base += (uint64_t)kLdsBlock * K) {
+    // count of slot sl (a packed slot keeps it in the low half of its last word)
+    auto count_at = [&](uint32_t sl) -> uint32_t { return PK ? (uint32_t)tc[sl] : cnt[sl]; };
+    for (uint64_t base = 0; base < lim; base += (uint64_t)B * K) {
         // every lane loads K keys (lanes past the run re-read its last key and
         // drop it), so all loads of the batch are in flight together
         uint64_t key[K][W];
         uint64_t ix[K];
 #pragma unroll
         for (int e = 0; e < K; e++) {
-            const uint64_t i = base + (uint64_t)e * kLdsBlock + tid;
+            const uint64_t i = base + (uint64_t)e * B + tid;
             ix[e] = i < lim ? i : lim - 1;
         }
 #pragma unroll
@@ -844,28 +889,29 @@ __device__ void stage_table(const CountArgs& a, const LdsArgs& l, const Lds& s, 
         uint32_t nk = 0;   // valid keys of this lane: a prefix of the batch
 #pragma unroll
         for (int e = 0; e < K; e++)
-            if (base + (uint64_t)e * kLdsBlock + tid < lim) nk = (uint32_t)e + 1;
+            if (base + (uint64_t)e * B + tid < lim) nk = (uint32_t)e + 1;
         if (spill) {
 #pragma unroll
             for (int e = 0; e < K; e++)
                 if ((uint32_t)e < nk) overflow_push<W>(a, key[e]);
+            if (l.probe_hist && nk) atomicAdd(&s.probes[0], nk);
         } else {
-            lds_insert_all<K, W>(a, w0, rest, cnt, C, l.theta, key, nk);
+            lds_insert_all<K, W, PK>(a, w0, rest, cnt, tc, C, l.theta, key, nk, l.probe_hist ? s.probes : nullptr);
         }
     }
     __syncthreads();
     // dump: count this thread's pairs, one reservation for the block (its
     // round trip overlaps the histogram), write
     uint32_t mine = 0;
-    for (uint32_t sl = tid; sl < C; sl += kLdsBlock) mine += cnt[sl] >= a.threshold;
+    for (uint32_t sl = tid; sl < C; sl += B) mine += count_at(sl) >= a.threshold;
     uint32_t total;
     const uint32_t pre = block_excl_scan(mine, wsum, total);
     uint64_t base = 0;
     if (tid == 0 && total) base = add_dev(a.n_out, (uint64_t)total);
     // most distinct keys occur once: count those per wave with one LDS add
-    for (uint32_t b0 = 0; b0 < C; b0 += kLdsBlock) {
+    for (uint32_t b0 = 0; b0 < C; b0 += B) {
         const uint32_t sl = b0 + tid;
-        const uint32_t c = sl < C ? cnt[sl] : 0u;
+        const uint32_t c = sl < C ? count_at(sl) : 0u;
         const uint64_t ones = __ballot(c == 1u);
         if (ones && __lane_id() == (uint32_t)__ffsll((unsigned long long)ones) - 1u)
             atomicAdd(&s.hist[1], (uint32_t)__popcll(ones));
@@ -878,13 +924,19 @@ __device__ void stage_table(const CountArgs& a, const LdsArgs& l, const Lds& s, 
     if (tid == 0) *s_base = base;
     __syncthreads();
     uint64_t pos = *s_base + pre;
-    for (uint32_t sl = tid; sl < C && mine; sl += kLdsBlock) {
-        const uint32_t c = cnt[sl];
+    for (uint32_t sl = tid; sl < C && mine; sl += B) {
+        const uint32_t c = count_at(sl);
         if (c && c >= a.threshold) {
             if (pos < a.cap) {
                 a.out_keys[pos * W] = w0[sl];
+                if (PK) {
 #pragma unroll
-                for (int i = 1; i < W; i++) a.out_keys[pos * W + i] = rest[(uint32_t)(i - 1) * C + sl];
+                    for (int i = 1; i + 1 < W; i++) a.out_keys[pos * W + i] = rest[(uint32_t)(i - 1) * C + sl];
+                    a.out_keys[pos * W + W - 1] = tc[sl] >> 32;
+                } else {
+#pragma unroll
+                    for (int i = 1; i < W; i++) a.out_keys[pos * W + i] = rest[(uint32_t)(i - 1) * C + sl];
+                }
                 a.out_counts[pos] = c;
             } else {
                 set_status(a.status, ST_OUT_CAP);
@@ -895,26 +947,31 @@ __device__ void stage_table(const CountArgs& a, const LdsArgs& l, const Lds& s, 
     }
 }
 
-template <int W>
+template <int W, uint32_t B, bool PK>
 __device__ __forceinline__ void run_stage(const CountArgs& a, const LdsArgs& l, const Lds& s, uint32_t st,
                                           uint32_t r, uint32_t local, uint32_t& wmax) {
     switch (st) {
-        case 0: stage_count<W>(a, l, s, r, local); break;
-        case 1: stage_scan(a, l, s, r); break;
-        case 2: stage_scatter<W>(a, l, s, r, local); break;
-        default: stage_table<W>(a, l, s, r, local, wmax); break;
+        case 0: stage_count<W, B>(a, l, s, r, local); break;
+        case 1: stage_scan<B>(a, l, s, r); break;
+        case 2: stage_scatter<W, B>(a, l, s, r, local); break;
+        default: stage_table<W, B, PK>(a, l, s, r, local, wmax); break;
     }
 }
 
-__device__ __forceinline__ void hist_begin(const Lds& s) {
-    for (uint32_t b = threadIdx.x; b < kLdsHist; b += kLdsBlock) s.hist[b] = 0;
+template <uint32_t B>
+__device__ __forceinline__ void hist_begin(const LdsArgs& l, const Lds& s) {
+    for (uint32_t b = threadIdx.x; b < kLdsHist; b += B) s.hist[b] = 0;
+    if (l.probe_hist && threadIdx.x < kProbeHist) s.probes[threadIdx.x] = 0;
     __syncthreads();
 }
-__device__ __forceinline__ void hist_end(const CountArgs& a, const Lds& s, uint32_t wmax) {
+template <uint32_t B>
+__device__ __forceinline__ void hist_end(const CountArgs& a, const LdsArgs& l, const Lds& s, uint32_t wmax) {
     flush_max(a.max_count, wmax);
     __syncthreads();
-    for (uint32_t b = threadIdx.x; b < kLdsHist; b += kLdsBlock)
+    for (uint32_t b = threadIdx.x; b < kLdsHist; b += B)
         if (s.hist[b]) add_dev(&a.hist[b], (uint64_t)s.hist[b]);
+    if (l.probe_hist && threadIdx.x < kProbeHist && s.probes[threadIdx.x])
+        add_dev(&l.probe_hist[threadIdx.x], (uint64_t)s.probes[threadIdx.x]);
 }
 
 // Segment of queue item `item` (last j < ns with start[j] <= item) and its
@@ -942,16 +999,17 @@ __device__ __forceinline__ uint32_t locate_item(const uint64_t* start, uint32_t 
 // segment search overlap with the stage's work. Dependencies point to earlier
 // items only, and the earliest unfinished item is always some workgroup's
 // current one, so holding one popped item ahead cannot deadlock.
-template <int W>
-__global__ void __launch_bounds__(kLdsBlock) k_lds_persistent(CountArgs a, LdsArgs l) {
+template <int W, uint32_t B, bool PK>
+__global__ void __launch_bounds__(B, 4) k_lds_persistent(CountArgs a, LdsArgs l) {
     extern __shared__ __align__(16) uint8_t lds_raw[];
     const Lds s = lds_carve(lds_raw);
     uint64_t* s_item = (uint64_t*)(lds_raw + kLdsHist * 4);
     uint64_t* s_first = s_item + 1;
     uint32_t* s_seg = (uint32_t*)(s_item + 2);
-    static_assert(kLdsHist * 4 + 24 <= kLdsReserved - 4, "queue scalars exceed the reserved LDS");
+    static_assert(kLdsHist * 4 + 24 <= kProbeHistAt && kProbeHistAt + 4 * kProbeHist <= kLdsReserved - 4,
+                  "queue scalars and probe counts exceed the reserved LDS");
     const uint32_t tid = threadIdx.x;
-    hist_begin(s);
+    hist_begin<B>(l, s);
     uint32_t wmax = 0;
     const uint32_t ns = *l.n_seg;
     const uint64_t total = l.seg_start[ns];
@@ -988,7 +1046,7 @@ __global__ void __launch_bounds__(kLdsBlock) k_lds_persistent(CountArgs a, LdsAr
         }
         __syncthreads();
         const uint64_t t0 = l.stage_clocks ? wall_clock64() : 0;
-        run_stage<W>(a, l, s, st, r, local, wmax);
+        run_stage<W, B, PK>(a, l, s, st, r, local, wmax);
         // Stages 0 and 1 publish with device-coherent stores and atomics, so a
         // drain before the signal suffices. The scatter writes its keys with
         // plain stores (merged in this XCD's L2): once every wave has drained
@@ -1027,69 +1085,80 @@ __global__ void __launch_bounds__(kLdsBlock) k_lds_persistent(CountArgs a, LdsAr
         }
         __syncthreads();
     }
-    hist_end(a, s, wmax);
+    hist_end<B>(a, l, s, wmax);
 }
 
 // PLAIN: `items` blocks of one stage of one rank.
-template <int W>
+template <int W, bool PK>
 __global__ void __launch_bounds__(kLdsBlock) k_lds_stage(CountArgs a, LdsArgs l, uint32_t st, uint32_t r) {
+    constexpr uint32_t B = kLdsBlock;
     extern __shared__ __align__(16) uint8_t lds_raw[];
     const Lds s = lds_carve(lds_raw);
-    hist_begin(s);
+    hist_begin<B>(l, s);
     uint32_t wmax = 0;
-    run_stage<W>(a, l, s, st, r, blockIdx.x, wmax);
+    run_stage<W, B, PK>(a, l, s, st, r, blockIdx.x, wmax);
     __syncthreads();
-    hist_end(a, s, wmax);
+    hist_end<B>(a, l, s, wmax);
 }
 
 // The LDS attribute is set on every launch: it belongs to the current device's
 // module, and a process-wide "already set" flag would race between threads
 // and miss other devices.
-template <int W>
+template <int W, uint32_t B, bool PK>
 static hipError_t persistent_lds_w(const CountArgs& a, const LdsArgs& l, uint32_t grid, hipStream_t s) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_lds_persistent<W>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       kLdsBytes);
+    hipError_t e = hipFuncSetAttribute((const void*)k_lds_persistent<W, B, PK>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, LdsShape<B>::bytes);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_lds_persistent<W>, dim3(grid), dim3(kLdsBlock), kLdsBytes, s, a, l);
+    hipLaunchKernelGGL((k_lds_persistent<W, B, PK>), dim3(grid), dim3(B), LdsShape<B>::bytes, s, a, l);
     return hipGetLastError();
 }
 
-template <int W>
+template <int W, bool PK>
 static hipError_t stage_lds_w(const CountArgs& a, const LdsArgs& l, uint32_t st, uint32_t r, uint32_t items,
                               hipStream_t s) {
     if (items == 0) return hipSuccess;
-    hipError_t e = hipFuncSetAttribute((const void*)k_lds_stage<W>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       kLdsBytes);
+    hipError_t e = hipFuncSetAttribute((const void*)k_lds_stage<W, PK>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       LdsShape<kLdsBlock>::bytes);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_lds_stage<W>, dim3(items), dim3(kLdsBlock), kLdsBytes, s, a, l, st, r);
+    hipLaunchKernelGGL((k_lds_stage<W, PK>), dim3(items), dim3(kLdsBlock), LdsShape<kLdsBlock>::bytes, s, a, l, st, r);
     return hipGetLastError();
 }
 
-hipError_t launch_lds_persistent(const CountArgs& a, const LdsArgs& l, uint32_t grid, hipStream_t s) {
+// Packed slots exist for keys of two words or more (lds_packed).
+template <uint32_t B>
+static hipError_t persistent_lds_b(const CountArgs& a, const LdsArgs& l, uint32_t grid, hipStream_t s) {
+    const bool pk = l.packed != 0;
     switch (a.W) {
-        case 1: return persistent_lds_w<1>(a, l, grid, s);
-        case 2: return persistent_lds_w<2>(a, l, grid, s);
-        case 3: return persistent_lds_w<3>(a, l, grid, s);
-        case 4: return persistent_lds_w<4>(a, l, grid, s);
-        case 5: return persistent_lds_w<5>(a, l, grid, s);
-        case 6: return persistent_lds_w<6>(a, l, grid, s);
-        case 7: return persistent_lds_w<7>(a, l, grid, s);
-        case 8: return persistent_lds_w<8>(a, l, grid, s);
+        case 1: return persistent_lds_w<1, B, false>(a, l, grid, s);
+        case 2: return pk ? persistent_lds_w<2, B, true>(a, l, grid, s) : persistent_lds_w<2, B, false>(a, l, grid, s);
+        case 3: return pk ? persistent_lds_w<3, B, true>(a, l, grid, s) : persistent_lds_w<3, B, false>(a, l, grid, s);
+        case 4: return pk ? persistent_lds_w<4, B, true>(a, l, grid, s) : persistent_lds_w<4, B, false>(a, l, grid, s);
+        case 5: return pk ? persistent_lds_w<5, B, true>(a, l, grid, s) : persistent_lds_w<5, B, false>(a, l, grid, s);
+        case 6: return pk ? persistent_lds_w<6, B, true>(a, l, grid, s) : persistent_lds_w<6, B, false>(a, l, grid, s);
+        case 7: return pk ? persistent_lds_w<7, B, true>(a, l, grid, s) : persistent_lds_w<7, B, false>(a, l, grid, s);
+        case 8: return pk ? persistent_lds_w<8, B, true>(a, l, grid, s) : persistent_lds_w<8, B, false>(a, l, grid, s);
     }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_lds_persistent(const CountArgs& a, const LdsArgs& l, uint32_t grid, hipStream_t s) {
+    if (l.block == 1024) return persistent_lds_b<1024>(a, l, grid, s);
+    if (l.block == 512) return persistent_lds_b<512>(a, l, grid, s);
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_lds_stage(const CountArgs& a, const LdsArgs& l, uint32_t st, uint32_t r, uint32_t items,
                             hipStream_t s) {
+    const bool pk = l.packed != 0;
     switch (a.W) {
-        case 1: return stage_lds_w<1>(a, l, st, r, items, s);
-        case 2: return stage_lds_w<2>(a, l, st, r, items, s);
-        case 3: return stage_lds_w<3>(a, l, st, r, items, s);
-        case 4: return stage_lds_w<4>(a, l, st, r, items, s);
-        case 5: return stage_lds_w<5>(a, l, st, r, items, s);
-        case 6: return stage_lds_w<6>(a, l, st, r, items, s);
-        case 7: return stage_lds_w<7>(a, l, st, r, items, s);
-        case 8: return stage_lds_w<8>(a, l, st, r, items, s);
+        case 1: return stage_lds_w<1, false>(a, l, st, r, items, s);
+        case 2: return pk ? stage_lds_w<2, true>(a, l, st, r, items, s) : stage_lds_w<2, false>(a, l, st, r, items, s);
+        case 3: return pk ? stage_lds_w<3, true>(a, l, st, r, items, s) : stage_lds_w<3, false>(a, l, st, r, items, s);
+        case 4: return pk ? stage_lds_w<4, true>(a, l, st, r, items, s) : stage_lds_w<4, false>(a, l, st, r, items, s);
+        case 5: return pk ? stage_lds_w<5, true>(a, l, st, r, items, s) : stage_lds_w<5, false>(a, l, st, r, items, s);
+        case 6: return pk ? stage_lds_w<6, true>(a, l, st, r, items, s) : stage_lds_w<6, false>(a, l, st, r, items, s);
+        case 7: return pk ? stage_lds_w<7, true>(a, l, st, r, items, s) : stage_lds_w<7, false>(a, l, st, r, items, s);
+        case 8: return pk ? stage_lds_w<8, true>(a, l, st, r, items, s) : stage_lds_w<8, false>(a, l, st, r, items, s);
     }
     return hipErrorInvalidValue;
 }

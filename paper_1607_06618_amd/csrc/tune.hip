@@ -1,5 +1,6 @@
 // Autotuner of the counting schedule: times gerbil_count over a small grid
-// of table placements, fill levels and pool sizes on the caller's bins and
+// of table placements, fill levels, pool sizes and workgroup shapes on the
+// caller's bins and
 // keeps the fastest choice that completes without a capacity error. Choices
 // are cached per (device, key width, m, bins, schedule, bin-size profile),
 // so later runs of the same shape skip the timing. The paper picks thread
@@ -23,6 +24,7 @@ struct Candidate {
     uint32_t table;
     float load;
     uint32_t pool;
+    uint32_t block;
 };
 
 using Key = std::tuple<int, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, int, int, int>;
@@ -36,24 +38,29 @@ std::vector<Candidate> candidates(const gerbil_params* p) {
     std::vector<Candidate> c;
     const bool batched = p->mode == GERBIL_BATCHED;
     if (p->table != GERBIL_TABLE_HBM && (p->k + 31) / 32 <= GERBIL_MAX_LDS_W) {
+        // LDS: one 1024-thread workgroup per CU, or two of 512 with half-size tables
         const float fills[] = {0.6f, 0.8f, 1.0f, 1.2f};
         const uint32_t pools[] = {4, 8, 16};
-        for (float f : fills) {
-            if (batched)
-                for (uint32_t q : pools) c.push_back({GERBIL_TABLE_LDS, f, q});
-            else
-                c.push_back({GERBIL_TABLE_LDS, f, 0});
+        for (uint32_t b : {1024u, 512u}) {
+            if (!batched && b != 1024u) continue;
+            for (float f : fills) {
+                if (batched)
+                    for (uint32_t q : pools) c.push_back({GERBIL_TABLE_LDS, f, q, b});
+                else
+                    c.push_back({GERBIL_TABLE_LDS, f, 0, b});
+            }
         }
     }
     if (p->table != GERBIL_TABLE_LDS) {
         const float loads[] = {0.4f, 0.6f};
         const uint32_t pools[] = {8, 32};
-        for (float f : loads) {
-            if (batched)
-                for (uint32_t q : pools) c.push_back({GERBIL_TABLE_HBM, f, q});
-            else
-                c.push_back({GERBIL_TABLE_HBM, f, 0});
-        }
+        for (uint32_t b : {256u, 512u, 1024u})
+            for (float f : loads) {
+                if (batched)
+                    for (uint32_t q : pools) c.push_back({GERBIL_TABLE_HBM, f, q, b});
+                else
+                    c.push_back({GERBIL_TABLE_HBM, f, 0, b});
+            }
     }
     return c;
 }
@@ -63,8 +70,10 @@ gerbil_params apply(const gerbil_params* p, const Candidate& c) {
     q.table = c.table;
     q.load_factor = c.load;
     q.pool = c.pool;
+    q.block = c.block;
     q.timing_events = nullptr;
     q.stage_clocks = nullptr;
+    q.probe_hist = nullptr;
     return q;
 }
 
@@ -117,9 +126,10 @@ int32_t gerbil_autotune(const gerbil_bins* bins, const gerbil_params* p, void* w
         std::lock_guard<std::mutex> lock(g_mu);
         auto it = g_cache.find(key);
         if (it != g_cache.end()) {
-            *best = apply(p, Candidate{it->second.table, it->second.load_factor, it->second.pool});
+            *best = apply(p, Candidate{it->second.table, it->second.load_factor, it->second.pool, it->second.block});
             best->timing_events = p->timing_events;
             best->stage_clocks = p->stage_clocks;
+            best->probe_hist = p->probe_hist;
             if (info) {
                 *info = it->second;
                 info->cached = 1;
@@ -144,7 +154,7 @@ int32_t gerbil_autotune(const gerbil_bins* bins, const gerbil_params* p, void* w
         gerbil_report rep;
         float ms_min = INFINITY;
         bool ok = true;
-        for (int rep_i = 0; rep_i < 3 && ok; rep_i++) {   // the first run is a warm-up
+        for (int rep_i = 0; rep_i < 2 && ok; rep_i++) {   // the first run is a warm-up
             if (hipEventRecord(e0, stream) != hipSuccess) { st = GERBIL_EDEVICE; break; }
             st = gerbil_count(bins, &q, ws, need, keys, counts, cap, &state, stream);
             if (st != GERBIL_OK) break;
@@ -168,6 +178,7 @@ int32_t gerbil_autotune(const gerbil_bins* bins, const gerbil_params* p, void* w
             res.table = c.table;
             res.load_factor = c.load;
             res.pool = c.pool;
+            res.block = c.block;
         }
     }
     (void)hipEventDestroy(e0);
@@ -179,9 +190,10 @@ int32_t gerbil_autotune(const gerbil_bins* bins, const gerbil_params* p, void* w
         std::lock_guard<std::mutex> lock(g_mu);
         g_cache[key] = res;
     }
-    *best = apply(p, Candidate{res.table, res.load_factor, res.pool});
+    *best = apply(p, Candidate{res.table, res.load_factor, res.pool, res.block});
     best->timing_events = p->timing_events;
     best->stage_clocks = p->stage_clocks;
+    best->probe_hist = p->probe_hist;
     if (info) *info = res;
     return GERBIL_OK;
 }

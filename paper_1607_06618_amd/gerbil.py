@@ -43,6 +43,7 @@ GERBIL_CEIL_HBM_ADD = 2
 GERBIL_CEIL_HBM_CAS = 3
 GERBIL_CEIL_HBM_LOAD = 4
 GERBIL_CEIL_ONE_ADDR = 5
+GERBIL_PROBE_HIST = 32
 GERBIL_FORMAT_DETECT = 0
 GERBIL_FORMAT_FASTQ = 1
 GERBIL_FORMAT_FASTA = 2
@@ -73,7 +74,7 @@ class gerbil_params(ctypes.Structure):
                 ("order", u32), ("bin_map", vp), ("mode", u32), ("table", u32), ("load_factor", f32),
                 ("max_probes", u32), ("block", u32), ("pool", u32), ("overflow_cap", u64),
                 ("superm_cap", u64), ("table_budget", u64), ("timing_events", vp), ("stage_clocks", vp),
-                ("size_sample", u32), ("reserved0", u32), ("rank_table", vp)]
+                ("size_sample", u32), ("reserved0", u32), ("rank_table", vp), ("probe_hist", vp)]
 
 
 class gerbil_encoded(ctypes.Structure):
@@ -108,7 +109,7 @@ class gerbil_pipeline(ctypes.Structure):
 
 class gerbil_tune_result(ctypes.Structure):
     _fields_ = [("table", u32), ("load_factor", f32), ("pool", u32), ("candidates", u32), ("cached", u32),
-                ("best_ms", f32)]
+                ("best_ms", f32), ("block", u32)]
 
 
 class gerbil_parsed(ctypes.Structure):
@@ -481,13 +482,14 @@ def make_params(k: int, m: int, n_bins: int, threshold: int, mode: int = GERBIL_
                 bin_map_ptr: int = 0, load_factor: float = 0.0, max_probes: int = 0, block: int = 0,
                 table: int = GERBIL_TABLE_AUTO, pool: int = 0, overflow_cap: int = 0, superm_cap: int = 0,
                 table_budget: int = 0, timing_events: int = 0, stage_clocks: int = 0,
-                size_sample: int = 0, canonical: bool = True, rank_table_ptr: int = 0) -> gerbil_params:
+                size_sample: int = 0, canonical: bool = True, rank_table_ptr: int = 0,
+                probe_hist: int = 0) -> gerbil_params:
     return gerbil_params(k=k, m=m, n_bins=n_bins, threshold=threshold, canonical=int(canonical), order=order,
                          bin_map=bin_map_ptr or None, mode=mode, table=table, load_factor=load_factor,
                          max_probes=max_probes, block=block, pool=pool, overflow_cap=overflow_cap,
                          superm_cap=superm_cap, table_budget=table_budget, timing_events=timing_events or None,
                          stage_clocks=stage_clocks or None, size_sample=size_sample,
-                         rank_table=rank_table_ptr or None)
+                         rank_table=rank_table_ptr or None, probe_hist=probe_hist or None)
 
 
 @dataclass
@@ -588,7 +590,7 @@ class Job:
         self.count()
 
     def autotune(self) -> gerbil_tune_result:
-        """Choose table placement, fill and pool by timing them on this job's bins
+        """Choose table placement, fill, pool and workgroup shape by timing them on this job's bins
         (after encode and bin); the job then counts with the choice."""
         torch = self.torch
         s = _stream_handle(self.stream)

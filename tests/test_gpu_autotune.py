@@ -38,7 +38,8 @@ def test_autotune_choice_counts_exactly_and_is_cached():
     job, info = tuned_job(a, o, w)
     assert info.cached == 0 and info.candidates > 0 and info.best_ms > 0
     assert info.table in (g.GERBIL_TABLE_LDS, g.GERBIL_TABLE_HBM)
-    assert job.p.table == info.table and job.p.pool == info.pool
+    assert job.p.table == info.table and job.p.pool == info.pool and job.p.block == info.block
+    assert info.block in ((512, 1024) if info.table == g.GERBIL_TABLE_LDS else (256, 512, 1024))
     assert abs(job.p.load_factor - info.load_factor) < 1e-6
     res = job.result()
     keys, counts = res.sorted()
@@ -47,7 +48,7 @@ def test_autotune_choice_counts_exactly_and_is_cached():
     # same shape again: the choice comes from the cache, nothing is timed
     job2, info2 = tuned_job(a, o, w)
     assert info2.cached == 1 and info2.candidates == info.candidates
-    assert (info2.table, info2.pool) == (info.table, info.pool)
+    assert (info2.table, info2.pool, info2.block) == (info.table, info.pool, info.block)
     res2 = job2.result()
     k2, c2 = res2.sorted()
     assert np.array_equal(k2, ref.keys) and np.array_equal(c2, ref.counts)

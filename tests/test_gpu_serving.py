@@ -114,3 +114,26 @@ def test_full_size_jobs_alone_and_mixed():
         assert ka.shape[0] == gold.int("n_pairs")
         got = shard_digests_host(ka, ca, w.k, gold.int("shard_mod"))
         assert [(n, d) for n, d in got] == [(n, d) for n, _, d in gold.shards], f"job {a_res.job_id}: pairs differ"
+
+
+def test_capacity_errors_are_retried_per_job():
+    """A job whose emergency area is too small (forced: one probe, a tiny
+    area) or whose output guess is too small is counted again with exact
+    sizes; its result is still the oracle's, and no other job is affected."""
+    n = 3
+    reqs, data = _requests(n, 0.01, np.zeros(n))
+
+    def tiny(p):
+        p.max_probes = 1
+        p.overflow_cap = 64
+
+    srv = serve.CountingServer(budget_bytes=64 << 30, max_inflight=3, params_hook=tiny)
+    res = srv.serve(reqs, realtime=False)
+    assert [r.job_id for r in res] == list(range(n))
+    assert all(r.retries == 1 and not r.error for r in res)
+    for r, (w, a, o) in zip(res, data):
+        ref = oracle.count(a, o, w.k, threshold=w.threshold)
+        k_, c_ = r.sorted()
+        assert np.array_equal(k_, ref.keys) and np.array_equal(c_, ref.counts)
+        assert np.array_equal(r.hist, ref.folded_hist(r.hist.size))
+        assert r.device_ms > 0 and r.count_kernel_ms > 0
