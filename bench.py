@@ -40,6 +40,8 @@ def parse_args(argv=None):
     ap.add_argument("--pool", type=int, default=0)
     ap.add_argument("--load", type=float, default=0.0)
     ap.add_argument("--table", default="lds", choices=["lds", "hbm"])
+    ap.add_argument("--theta", type=int, default=0, help="probes per key before the emergency area (0: default)")
+    ap.add_argument("--overflow-cap", type=int, default=0, help="emergency-area capacity in keys (0: default)")
     ap.add_argument("--block", type=int, default=0,
                     help="threads per counting workgroup (LDS tables: 512 = two workgroups per CU)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU-oracle sample")
@@ -298,7 +300,7 @@ def main(argv=None):
         if w.k > 256 and args.table == "lds":
             table = g.GERBIL_TABLE_HBM   # LDS tables hold keys of up to 256 bases
         p = g.make_params(w.k, w.m, w.n_bins, w.threshold, mode=mode, pool=args.pool, load_factor=args.load, table=table,
-                          block=args.block,
+                          block=args.block, max_probes=args.theta, overflow_cap=args.overflow_cap,
                           canonical=not args.non_canonical, size_sample=args.size_sample,
                           bin_map_ptr=bin_map_d.data_ptr() if bin_map_d is not None else 0,
                           timing_events=ctypes.addressof(ev))
@@ -416,6 +418,7 @@ def main(argv=None):
              ("batched", "hbm"): "k_count_persistent", ("plain", "hbm"): "k_count_bin+k_compact"}[(head, head_table)]
     traffic = None
     default_schedule = (not args.tune and args.load == 0.0 and args.pool == 0 and args.scale == 1.0 and args.block == 0
+                        and args.theta == 0 and args.overflow_cap == 0
                         and not args.non_canonical and args.size_sample == 0)
     if default_schedule and "+" not in kname:
         traffic = measured_traffic(kname, w.name)

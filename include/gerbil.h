@@ -109,7 +109,9 @@ typedef struct {
                                 stages overlap on the CU); any other value one 1024-thread
                                 workgroup per CU with 160 KB. LDS tables, PLAIN: always 1024     */
     uint32_t pool;           /* BATCHED: hash tables resident at once; 0 = chosen from budget    */
-    uint64_t overflow_cap;   /* emergency-area capacity in keys; 0 = default                     */
+    uint64_t overflow_cap;   /* emergency-area capacity in k-mer occurrences, rounded up to a power
+                                of two, at most 2^31; 0 = 2^20. The workspace holds the area and
+                                its counting table of twice as many slots                        */
     uint64_t superm_cap;     /* super-mer descriptor capacity; 0 = default estimate              */
     uint64_t table_budget;   /* bytes of workspace for hash tables; 0 = default                  */
     hipEvent_t* timing_events; /* optional hipEvent_t[2] recorded on the stream just before and just

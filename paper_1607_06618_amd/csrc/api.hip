@@ -137,6 +137,8 @@ int32_t check_params(const gerbil_params* p) {
     if (p->k > 32 * GERBIL_MAX_W) return GERBIL_EUNSUPPORTED;
     if (p->table == GERBIL_TABLE_LDS && (p->k + 31) / 32 > GERBIL_MAX_LDS_W) return GERBIL_EUNSUPPORTED;
     if (p->canonical > 1) return GERBIL_EINVAL;
+    // the emergency area's counting table refers to keys by a 32-bit index
+    if (p->overflow_cap > (1ull << 31)) return GERBIL_EINVAL;
     return GERBIL_OK;
 }
 
@@ -148,6 +150,9 @@ struct CountLayout {
     uint64_t* scalars;   // [0] n_out [1] n_ovf [2] max_count [3] status
     uint64_t* hist;
     uint64_t* ovf_keys;
+    uint32_t* ovf_state;
+    uint64_t* ovf_tkeys;
+    uint32_t* ovf_tcnt;
     // batched plan
     uint32_t *order, *nb, *n_ins, *n_cmp, *ins_done, *cmp_done, *seg_code;
     uint64_t *seg_start, *cursor;
@@ -176,6 +181,9 @@ uint64_t count_fixed(uint32_t W, uint64_t ovf_cap, uint32_t n_bins, bool batched
     l.scalars = c.take<uint64_t>(8);
     l.hist = c.take<uint64_t>(kHistInternal);
     l.ovf_keys = c.take<uint64_t>(ovf_cap * W);
+    l.ovf_state = c.take<uint32_t>(ovf_table_slots(ovf_cap));
+    l.ovf_tkeys = c.take<uint64_t>(ovf_table_slots(ovf_cap) * W);
+    l.ovf_tcnt = c.take<uint32_t>(ovf_table_slots(ovf_cap));
     if (batched) {
         l.order = c.take<uint32_t>(n_bins);
         l.nb = c.take<uint32_t>(n_bins);
@@ -352,6 +360,9 @@ CountArgs count_args(const gerbil_params* p, const gerbil_bins* bins, const gerb
     a.canonical = p->canonical;
     a.seed = kHashSeed;
     a.ovf_keys = L.ovf_keys;
+    a.ovf_state = L.ovf_state;
+    a.ovf_tkeys = L.ovf_tkeys;
+    a.ovf_tcnt = L.ovf_tcnt;
     a.ovf_cap = state->overflow_cap;
     a.n_ovf = state->n_overflow;
     a.out_keys = keys;
@@ -675,6 +686,9 @@ int32_t gerbil_count(const gerbil_bins* bins, const gerbil_params* p, void* ws, 
     a.canonical = p->canonical;
     a.seed = kHashSeed;
     a.ovf_keys = L.ovf_keys;
+    a.ovf_state = L.ovf_state;
+    a.ovf_tkeys = L.ovf_tkeys;
+    a.ovf_tcnt = L.ovf_tcnt;
     a.ovf_cap = ovf_cap;
     a.n_ovf = state->n_overflow;
     a.out_keys = keys;

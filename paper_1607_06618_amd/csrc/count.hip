@@ -1,6 +1,6 @@
 // Plain schedule of the counting step: one launch sequence per bin (insert
 // kernel, then the dump of its table), bins in order, one table reused; plus
-// the emergency-area sort-and-count that runs after all bins. The table logic
+// the counting of the emergency area that runs after all bins. The table logic
 // (Alg. 1, publication of multi-word keys, dump) is in table.h.
 #include "table.h"
 
@@ -65,13 +65,6 @@ __global__ void __launch_bounds__(256) k_compact(CountArgs a, Table t, uint64_t 
 
 // ------------------------------------------------------ emergency area
 template <int W>
-__device__ __forceinline__ bool key_less(const uint64_t* x, const uint64_t* y) {
-#pragma unroll
-    for (int i = 0; i < W; i++)
-        if (x[i] != y[i]) return x[i] < y[i];
-    return false;
-}
-template <int W>
 __device__ __forceinline__ bool key_eq(const uint64_t* x, const uint64_t* y) {
     bool e = true;
 #pragma unroll
@@ -79,71 +72,98 @@ __device__ __forceinline__ bool key_eq(const uint64_t* x, const uint64_t* y) {
     return e;
 }
 
-// Sort-and-count of the emergency area (Sec. 3.4.3). One workgroup: bitonic
-// sort of the keys in place (padded to a power of two with all-ones keys,
-// which no canonical key equals), then run-length counting. This path is
-// expected to be empty at sensible load factors; it exists for exactness.
-template <int W>
-__global__ void __launch_bounds__(1024) k_overflow(CountArgs a) {
-    const uint32_t tid = threadIdx.x, B = blockDim.x;
-    uint64_t n = ld_dev(a.n_ovf);
-    if (n > a.ovf_cap) n = a.ovf_cap;
+// Keys that did not fit in a table (theta probes failed, a sampled run
+// overflowed, or the first word is the empty-slot marker) were appended to the
+// emergency area (Sec. 3.4.3, where the paper sorts and compresses them). Here
+// they are counted in an open-addressing table in HBM with at least twice as
+// many slots as the area holds keys, so linear probing always ends at the key
+// or at a free slot: exact, with no probe limit. A slot's state word holds the
+// area index + 1 of the first occurrence that claimed it (by CAS on zero);
+// another occurrence compares its key with that occurrence in the area, which
+// no kernel writes any more, so nothing has to be published; every occurrence
+// then adds one to its slot's count. Many workgroups insert; the table is then
+// dumped (threshold, histogram). The table has next_pow2(2 n) slots for n keys,
+// read on the device, so an empty area costs three launches that return at once.
+constexpr uint32_t kOvfBlock = 256;
+
+__device__ __forceinline__ uint64_t ovf_n(const CountArgs& a) {
+    const uint64_t n = ld_dev(a.n_ovf);
+    return n < a.ovf_cap ? n : a.ovf_cap;
+}
+__device__ __forceinline__ uint64_t ovf_slots(uint64_t n) {
+    uint64_t t = 2;
+    while (t < 2 * n) t <<= 1;
+    return t;
+}
+
+__global__ void __launch_bounds__(kOvfBlock) k_ovf_clear(CountArgs a) {
+    const uint64_t n = ovf_n(a);
     if (n == 0) return;
-    uint64_t N = 1;
-    while (N < n) N <<= 1;   // ovf capacity is a power of two, so N <= capacity
-    uint64_t* K = a.ovf_keys;
-    for (uint64_t i = n + tid; i < N; i += B)
-        for (int w = 0; w < W; w++) K[i * W + w] = ~0ull;
-    __syncthreads();
-    for (uint64_t size = 2; size <= N; size <<= 1) {
-        for (uint64_t stride = size >> 1; stride > 0; stride >>= 1) {
-            for (uint64_t i = tid; i < N / 2; i += B) {
-                uint64_t lo = 2 * stride * (i / stride) + (i % stride), hi = lo + stride;
-                bool asc = (lo & size) == 0;
-                uint64_t x[W], y[W];
+    const uint64_t T = ovf_slots(n);
+    for (uint64_t i = (uint64_t)blockIdx.x * kOvfBlock + threadIdx.x; i < T; i += (uint64_t)gridDim.x * kOvfBlock) {
+        a.ovf_state[i] = 0u;
+        a.ovf_tcnt[i] = 0u;
+    }
+}
+
+template <int W>
+__global__ void __launch_bounds__(kOvfBlock) k_ovf_insert(CountArgs a) {
+    const uint64_t n = ovf_n(a);
+    if (n == 0) return;
+    const uint64_t T = ovf_slots(n), mask = T - 1;
+    for (uint64_t i = (uint64_t)blockIdx.x * kOvfBlock + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kOvfBlock) {
+        const uint64_t* key = a.ovf_keys + i * W;
+        uint64_t kw[W];
 #pragma unroll
-                for (int w = 0; w < W; w++) { x[w] = K[lo * W + w]; y[w] = K[hi * W + w]; }
-                bool swap = asc ? key_less<W>(y, x) : key_less<W>(x, y);
-                if (swap) {
-#pragma unroll
-                    for (int w = 0; w < W; w++) { K[lo * W + w] = y[w]; K[hi * W + w] = x[w]; }
-                }
+        for (int w = 0; w < W; w++) kw[w] = key[w];
+        uint64_t s = key_hash<W>(kw, a.seed ^ 0x9E3779B97F4A7C15ull) & mask;
+        for (uint64_t probe = 0; probe < T; probe++, s = (s + 1) & mask) {
+            const uint32_t found = cas_dev(&a.ovf_state[s], 0u, (uint32_t)(i + 1));
+            if (found == 0u || key_eq<W>(a.ovf_keys + (uint64_t)(found - 1) * W, kw)) {
+                add_dev(&a.ovf_tcnt[s], 1u);
+                break;
             }
-            __syncthreads();
         }
     }
+}
+
+template <int W>
+__global__ void __launch_bounds__(kOvfBlock) k_ovf_dump(CountArgs a) {
+    __shared__ uint32_t lh[kLdsHist];
+    const uint32_t tid = threadIdx.x;
+    const uint64_t n = ovf_n(a);
+    if (n == 0) return;
+    const uint64_t T = ovf_slots(n);
+    for (uint32_t b = tid; b < kLdsHist; b += kOvfBlock) lh[b] = 0;
+    __syncthreads();
     uint32_t wmax = 0;
-    for (uint64_t base = 0; base < n; base += B) {
-        uint64_t i = base + tid;
-        bool is_start = i < n && (i == 0 || !key_eq<W>(K + i * W, K + (i - 1) * W));
-        uint64_t c = 0;
-        if (is_start) {
-            uint64_t j = i + 1;
-            while (j < n && key_eq<W>(K + j * W, K + i * W)) j++;
-            c = j - i;
-            add_dev(&a.hist[c < kHistInternal - 1 ? c : kHistInternal - 1], 1ull);
-            if (c >= 0xFFFFFFFFull) set_status(a.status, ST_COUNT_SAT);
-            uint32_t c32 = c > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)c;
-            wmax = c32 > wmax ? c32 : wmax;
+    // every lane runs the same number of iterations (wave_reserve needs the whole wave)
+    for (uint64_t base = (uint64_t)blockIdx.x * kOvfBlock; base < T; base += (uint64_t)gridDim.x * kOvfBlock) {
+        const uint64_t s = base + tid;
+        const uint32_t rep = s < T ? a.ovf_state[s] : 0u;
+        const uint32_t c = rep ? a.ovf_tcnt[s] : 0u;
+        if (c) {
+            if (c < kLdsHist) atomicAdd(&lh[c], 1u);
+            else add_dev(&a.hist[c < kHistInternal - 1 ? c : kHistInternal - 1], 1ull);
+            wmax = c > wmax ? c : wmax;
         }
-        bool emit = is_start && c >= a.threshold;
-        uint64_t pos = wave_reserve(a.n_out, emit);
+        const bool emit = c && c >= a.threshold;
+        const uint64_t pos = wave_reserve(a.n_out, emit);
         if (emit) {
             if (pos < a.cap) {
+                const uint64_t* key = a.ovf_keys + (uint64_t)(rep - 1) * W;
 #pragma unroll
-                for (int w = 0; w < W; w++) a.out_keys[pos * W + w] = K[i * W + w];
-                a.out_counts[pos] = (uint32_t)c;
+                for (int w = 0; w < W; w++) a.out_keys[pos * W + w] = key[w];
+                a.out_counts[pos] = c;
             } else {
                 set_status(a.status, ST_OUT_CAP);
             }
         }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        uint32_t y = __shfl_xor(wmax, off);
-        wmax = y > wmax ? y : wmax;
-    }
-    if (__lane_id() == 0 && wmax)
-        __hip_atomic_fetch_max(a.max_count, (uint64_t)wmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    flush_max(a.max_count, wmax);
+    __syncthreads();
+    for (uint32_t b = tid; b < kLdsHist; b += kOvfBlock)
+        if (lh[b]) add_dev(&a.hist[b], (uint64_t)lh[b]);
 }
 
 // ------------------------------------------------------------ launchers
@@ -163,9 +183,18 @@ static hipError_t compact_w(const CountArgs& a, const Table& t, uint32_t nb, hip
     hipLaunchKernelGGL(k_compact<W>, dim3(g), dim3(256), 0, s, a, t, n_slots);
     return hipGetLastError();
 }
+// Grid of the emergency-area kernels: enough workgroups for the largest area;
+// each returns at once when the area is empty.
+static uint32_t ovf_grid(const CountArgs& a) {
+    const uint64_t blocks = (2 * a.ovf_cap + kOvfBlock - 1) / kOvfBlock;
+    return (uint32_t)(blocks < 2048 ? blocks : 2048);
+}
 template <int W>
 static hipError_t overflow_w(const CountArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_overflow<W>, dim3(1), dim3(1024), 0, s, a);
+    const uint32_t g = ovf_grid(a);
+    hipLaunchKernelGGL(k_ovf_clear, dim3(g), dim3(kOvfBlock), 0, s, a);
+    hipLaunchKernelGGL(k_ovf_insert<W>, dim3(g), dim3(kOvfBlock), 0, s, a);
+    hipLaunchKernelGGL(k_ovf_dump<W>, dim3(g), dim3(kOvfBlock), 0, s, a);
     return hipGetLastError();
 }
 

@@ -76,6 +76,10 @@ struct CountArgs {
     uint64_t* ovf_keys;   // [ovf_cap * W]
     uint64_t ovf_cap;
     uint64_t* n_ovf;
+    // its counting table: ovf_slots = 2 ovf_cap (a power of two) slots
+    uint32_t* ovf_state;  // [ovf_slots] 0 free, 1 being claimed, 2 published
+    uint64_t* ovf_tkeys;  // [ovf_slots * W]
+    uint32_t* ovf_tcnt;   // [ovf_slots]
     // output
     uint64_t* out_keys;   // [cap * W]
     uint32_t* out_counts;
@@ -250,7 +254,9 @@ hipError_t launch_count_bin(const CountArgs& a, const Table& t, uint32_t nb, uin
                             uint32_t block, hipStream_t s);
 // PLAIN: compact nb buckets of a table (emit, histogram, reset).
 hipError_t launch_compact(const CountArgs& a, const Table& t, uint32_t nb, hipStream_t s);
-// Emergency area: sort-and-count every key that did not fit in a table.
+// Emergency area: count every key that did not fit in a table (clear, insert and
+// dump its counting table; many workgroups, no host synchronisation).
 hipError_t launch_overflow(const CountArgs& a, hipStream_t s);
+inline uint64_t ovf_table_slots(uint64_t ovf_cap) { return 2 * ovf_cap; }
 
 }  // namespace gerbil

@@ -57,7 +57,8 @@ def test_param_validation_before_launch():
                 g.make_params(32, 7, 0, 2), g.make_params(32, 7, 5000, 2), g.make_params(32, 7, 64, 0),
                 g.make_params(32, 7, 64, 2, block=100),
                 g.make_params(32, 7, 64, 2, load_factor=0.99, table=g.GERBIL_TABLE_HBM),
-                g.make_params(32, 7, 64, 2, load_factor=4.5)):
+                g.make_params(32, 7, 64, 2, load_factor=4.5),
+                g.make_params(32, 7, 64, 2, overflow_cap=(1 << 31) + 1)):
         with pytest.raises(g.GerbilError) as e:
             g.gerbil_bin_workspace(enc, bad)
         assert e.value.status == g.GERBIL_EINVAL

@@ -321,3 +321,20 @@ def test_sampled_run_sizes_spill_to_the_emergency_area_exactly():
             else:
                 spilled.append(res.report.n_overflow)
     assert max(spilled) > 0, "no sampled run overflowed: the spill path was not exercised"
+
+
+@pytest.mark.parametrize("table", [g.GERBIL_TABLE_LDS, g.GERBIL_TABLE_HBM])
+def test_large_emergency_area_is_exact(table):
+    """A workload of 1.7 M windows counted with a single probe per key and full
+    tables, so that many of its occurrences are counted in the emergency area
+    by its multi-workgroup table (hundreds of thousands with single-slot LDS
+    probes; thousands with the 8-slot buckets of HBM tables)."""
+    w = synth.CONFIGS["c2_k65"].scaled(0.001)
+    a, o = w.generate()
+    ref = oracle.count(a, o, w.k, threshold=2)
+    res = g.count_kmers(a, o, w.k, w.m, 64, 2, 256, mode=g.GERBIL_BATCHED, table=table, max_probes=1,
+                        load_factor=1.2 if table == g.GERBIL_TABLE_LDS else 0.95, overflow_cap=1 << 22)
+    assert res.report.n_overflow > (100_000 if table == g.GERBIL_TABLE_LDS else 1_000), res.report.n_overflow
+    keys, counts = res.sorted()
+    assert np.array_equal(keys, ref.keys) and np.array_equal(counts, ref.counts)
+    assert np.array_equal(res.hist, ref.folded_hist(256))
