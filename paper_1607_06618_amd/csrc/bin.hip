@@ -35,6 +35,19 @@ constexpr uint32_t kMaxWLong = 32 * GERBIL_MAX_W;
 template <uint32_t MW> constexpr uint32_t rank_len() { return kTile + MW; }
 constexpr uint32_t kWordsPerTile = kTile / 64;
 
+// The same rank for m-mers held in 32 bits (m <= 15: 30 bits; the moved codes
+// c + 4^m stay below 2^31).
+__device__ __forceinline__ uint32_t rank_of32(uint32_t fw, uint32_t rc, uint32_t m, uint32_t order,
+                                              const uint32_t* __restrict__ table) {
+    uint32_t c = fw < rc ? fw : rc;
+    if (order == GERBIL_ORDER_TABLE) return table[c];
+    if (order == 0 && m >= 3) {
+        const uint32_t head = c >> (2 * m - 6);
+        if (head == 0 /* AAA */ || head == 4 /* ACA */) c += 1u << (2 * m);
+    }
+    return c;
+}
+
 __device__ __forceinline__ uint32_t rank_of(uint64_t fw, uint64_t rc, uint32_t m, uint32_t order,
                                             const uint32_t* __restrict__ table) {
     uint64_t c = fw < rc ? fw : rc;
@@ -51,6 +64,7 @@ constexpr uint32_t kMinPer = (kTile + 1 + kBinBlock - 1) / kBinBlock;      // mi
 // The bases a thread's ranks need (kRankPer m-mers, m <= 15) start at most 31
 // bases into a packed word, so they lie in that word and the next.
 static_assert(31 + rank_per<kMaxWLong>() - 1 + 15 <= 64, "a rank run must fit in two packed words");
+static_assert(15 + rank_per<kMaxWLong>() - 1 <= 32, "a rank run must fit in the 32 bases from its start");
 static_assert(kWordsPerTile <= kBinBlock, "one bitmap word per thread");
 
 // Position of the n-th (from 0) set bit of x; x has more than n set bits.
@@ -134,20 +148,25 @@ __global__ void __launch_bounds__(kBinBlock, 7) k_bin_tiles(BinArgs a) {
             const uint32_t i1 = i0 + kRankPer < len ? i0 + kRankPer : len;
             const int64_t j0 = P0 - 1 + (int64_t)i0;
             const uint32_t s0 = (uint32_t)(j0 & 31);
-            uint64_t fw = 0, rc = 0;
+            // the run's first m-mer and the bases rolled in after it all lie in the
+            // 32 bases from s0 (m + kRankPer - 1 <= 32); 32-bit arithmetic throughout
+            uint32_t fw = 0, rc = 0;
+            uint64_t nb = 0;   // the bases still to roll in, first one in the top two bits
             if (i0 < i1) {
                 const uint64_t win = s0 ? ((f.w0 << (2 * s0)) | (f.w1 >> (64 - 2 * s0))) : f.w0;
-                fw = win >> (64 - 2 * a.m);
-                rc = revcomp32(win) & mmask;
+                fw = (uint32_t)(win >> (64 - 2 * a.m));
+                rc = (uint32_t)(revcomp32(win) & mmask);
+                nb = win << (2 * a.m);
             }
+            const int64_t n_left = (int64_t)n_pos - (P0 - 1 + (int64_t)i0);   // positions of this run in range
             for (uint32_t i = i0; i < i1; i++) {
-                const int64_t j = P0 - 1 + (int64_t)i;
                 if (i > i0) {
-                    const uint64_t b2 = pair_base(f.w0, f.w1, s0 + (i - i0) + a.m - 1);
-                    fw = ((fw << 2) | b2) & mmask;
-                    rc = (rc >> 2) | ((3ull - b2) << (2 * a.m - 2));
+                    const uint32_t b2 = (uint32_t)(nb >> 62);
+                    nb <<= 2;
+                    fw = ((fw << 2) | b2) & code_mask;
+                    rc = (rc >> 2) | ((3u - b2) << (2 * a.m - 2));
                 }
-                R[i] = j < (int64_t)n_pos ? rank_of(fw, rc, a.m, a.order, a.rank_table) : 0xFFFFFFFFu;
+                R[i] = (int64_t)(i - i0) < n_left ? rank_of32(fw, rc, a.m, a.order, a.rank_table) : 0xFFFFFFFFu;
             }
             if (tid < kWordsPerTile) okS[tid] = f.ok;
         }
