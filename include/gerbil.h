@@ -108,7 +108,9 @@ typedef struct {
                                 workgroups per CU with 80 KB of LDS each (half-size tables whose
                                 stages overlap on the CU); any other value one 1024-thread
                                 workgroup per CU with 160 KB. LDS tables, PLAIN: always 1024     */
-    uint32_t pool;           /* BATCHED: hash tables resident at once; 0 = chosen from budget    */
+    uint32_t pool;           /* BATCHED: hash tables resident at once. LDS tables: key slots (ranks
+                                scattered and not yet counted), 0 = 16, best a multiple of 8 (one
+                                work queue per XCD); HBM tables: 0 = chosen from budget          */
     uint64_t overflow_cap;   /* emergency-area capacity in k-mer occurrences, rounded up to a power
                                 of two, at most 2^31; 0 = 2^20. The workspace holds the area and
                                 its counting table of twice as many slots                        */
@@ -349,7 +351,7 @@ int32_t gerbil_autotune_workspace(const gerbil_bins* bins, const gerbil_params* 
                                   hipStream_t stream);
 
 /* Time gerbil_count on `bins` for each candidate of the grid (LDS tables:
- * load_factor 0.6/0.8/1.0/1.2 x pool 4/8/16 x block 1024/512; HBM tables:
+ * load_factor 0.6/0.8/1.0/1.2 x pool 8/16/24 x block 1024/512; HBM tables:
  * load_factor 0.4/0.6 x pool 8/32 x block 256/512/1024; p->table = LDS or
  * HBM restricts the grid to that placement; PLAIN mode has no pool and LDS
  * tables only block 1024) and write into *best a copy of *p with table,

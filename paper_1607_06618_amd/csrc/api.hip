@@ -212,7 +212,10 @@ bool use_lds(const gerbil_params* p) {
     return p->table == GERBIL_TABLE_LDS || (p->table == GERBIL_TABLE_AUTO && (p->k + 31) / 32 <= GERBIL_MAX_LDS_W);
 }
 
-constexpr uint32_t kDefaultKeySlots = 8;
+// Two key slots per XCD queue: with slots a multiple of the queues, a rank and
+// the earlier rank whose slot it reuses sit in the same queue, and each XCD
+// scatters one rank while it counts the tables of the one before.
+constexpr uint32_t kDefaultKeySlots = 2 * kLdsQueues;
 constexpr uint32_t kDefaultLdsTheta = 64;   // single-slot probes are cheap in LDS
 constexpr double kDefaultLdsFill = 0.8;     // k-mers per LDS slot (distinct keys are fewer)
 
@@ -304,9 +307,9 @@ uint64_t lds_fixed(const LdsSizing& z, void* ws, uint64_t start, LdsLayout* L) {
     l.sp_cur = c.take<uint32_t>(z.sp_cap);
     l.sp_off = c.take<uint64_t>(z.sp_cap);
     l.done = c.take<uint32_t>(4ull * z.ranks_cap);
-    l.seg_start = c.take<uint64_t>(4ull * ((uint64_t)z.ranks_cap + 3 + z.lag) + 1);
+    l.seg_start = c.take<uint64_t>(kLdsQueues * (4ull * ((uint64_t)z.ranks_cap + 3 + z.lag) + 1));
     l.n_seg = c.take<uint32_t>(4);
-    l.cursor = c.take<uint64_t>(4);
+    l.cursor = c.take<uint64_t>(kLdsQueues * kCursorStride);
     l.keys = ws ? (uint64_t*)((uint8_t*)ws + start + c.used) : nullptr;
     if (L) *L = l;
     return c.used;
@@ -396,8 +399,11 @@ int32_t count_lds(const gerbil_bins* bins, const gerbil_params* p, void* ws, uin
     fill_state(state, p, bins, cap, ovf_cap, L);
     CountArgs a = count_args(p, bins, state, keys, counts, cap, L);
 
+    // one 1024-thread workgroup per CU, or two of 512
+    const uint32_t grid = batched ? (uint32_t)device_cus() * (kLdsBlock / z.block) : 1u;
     LdsArgs l;
     l.block = z.block;
+    l.n_queues = std::max<uint32_t>(1, std::min(kLdsQueues, grid));
     l.max_sub = z.max_sub;
     l.n_bins = p->n_bins;
     l.ranks_cap = z.ranks_cap;
@@ -442,8 +448,6 @@ int32_t count_lds(const gerbil_bins* bins, const gerbil_params* p, void* ws, uin
     if (e != hipSuccess) return GERBIL_EDEVICE;
     if (batched) {
         if (p->timing_events) e = hipEventRecord(p->timing_events[0], stream);
-        // one 1024-thread workgroup per CU, or two of 512
-        const uint32_t grid = (uint32_t)device_cus() * (kLdsBlock / z.block);
         if (e == hipSuccess) e = launch_lds_persistent(a, l, grid, stream);
         if (e == hipSuccess && p->timing_events) e = hipEventRecord(p->timing_events[1], stream);
     } else {

@@ -202,8 +202,17 @@ inline uint32_t lds_table_slots(uint32_t W, uint32_t B, bool packed) {
     }
 }
 
+// Work queues of the batched LDS schedule: one per XCD (MI355X has 8, each
+// with its own L2). Rank r belongs to queue r mod n_queues, and workgroup i
+// starts on queue i mod n_queues: workgroups are dispatched to the XCDs in
+// turn, so the scatter items of a rank run on one XCD and the partly filled
+// lines of its sub-table runs merge in one L2. Cursors sit 256 bytes apart.
+constexpr uint32_t kLdsQueues = 8;
+constexpr uint32_t kCursorStride = 32;
+
 struct LdsArgs {
     uint32_t block;           // threads per workgroup: 1024 or 512 (LdsShape)
+    uint32_t n_queues;        // work queues (1 .. kLdsQueues, at most the grid)
     uint32_t max_sub;         // LdsShape<block>::max_sub
     uint32_t n_bins, ranks_cap;
     uint32_t* n_ranks;        // scalar (plan output)
@@ -236,9 +245,9 @@ struct LdsArgs {
     const uint64_t* bin_off;
     const uint64_t* bin_kmers;
     uint32_t* done;           // [4 * ranks_cap] finished items per (rank, stage)
-    uint64_t* seg_start;      // [4 * (ranks_cap + 3 + lag) + 1]
+    uint64_t* seg_start;      // [kLdsQueues][4 * (ranks_cap + 3 + lag) + 1]: queue q at q * (n_seg + 1)
     uint32_t* n_seg;          // scalar
-    uint64_t* cursor;
+    uint64_t* cursor;         // [kLdsQueues * kCursorStride]: queue q at q * kCursorStride
     const uint64_t* n_superm;
     uint64_t superm_cap;
     uint32_t* status;

@@ -151,17 +151,19 @@ __global__ void __launch_bounds__(1024) k_lds_plan(LdsArgs l) {
         l.sp_cnt[j] = 0;
         l.sp_cur[j] = 0;
     }
-    // 3. queue segments: items per segment, then their prefix
+    // 3. queue segments: items per segment, then their prefix, for every
+    // queue (a queue holds the items of its ranks, in the same segment order)
     const uint32_t L = l.lag;
     const uint32_t ticks = R + 3 + L;
     const uint32_t ns = 4 * ticks;
+    const uint32_t NQ = l.n_queues;
     const uint32_t lag[4] = {0u, 1u, 2u, 2u + L};
     const uint32_t sper = (ns + 1023) / 1024;
-    auto items = [&](uint32_t seg) -> uint64_t {
+    auto items = [&](uint32_t seg, uint32_t q) -> uint64_t {
         uint32_t st = seg & 3, tick = seg >> 2;
         if (tick < lag[st]) return 0;
         uint32_t r = tick - lag[st];
-        if (r >= R) return 0;
+        if (r >= R || r % NQ != q) return 0;
         uint32_t nc = l.rank_nchunk[r];
         if (nc == 0) return 0;
         switch (st) {
@@ -171,32 +173,36 @@ __global__ void __launch_bounds__(1024) k_lds_plan(LdsArgs l) {
             default: return l.rank_nsub[r];
         }
     };
-    sum = 0;
-    for (uint32_t e = 0; e < sper; e++) {
-        uint32_t j = tid * sper + e;
-        if (j < ns) sum += items(j);
-    }
-    part[tid] = sum;
-    __syncthreads();
-    for (uint32_t off = 1; off < 1024; off <<= 1) {
-        uint64_t y = tid >= off ? part[tid - off] : 0ull;
-        __syncthreads();
-        part[tid] += y;
-        __syncthreads();
-    }
-    uint64_t run = tid ? part[tid - 1] : 0ull;
-    for (uint32_t e = 0; e < sper; e++) {
-        uint32_t j = tid * sper + e;
-        if (j < ns) {
-            l.seg_start[j] = run;
-            run += items(j);
+    for (uint32_t q = 0; q < NQ; q++) {
+        uint64_t* start = l.seg_start + (uint64_t)q * (ns + 1);
+        sum = 0;
+        for (uint32_t e = 0; e < sper; e++) {
+            uint32_t j = tid * sper + e;
+            if (j < ns) sum += items(j, q);
         }
+        part[tid] = sum;
+        __syncthreads();
+        for (uint32_t off = 1; off < 1024; off <<= 1) {
+            uint64_t y = tid >= off ? part[tid - off] : 0ull;
+            __syncthreads();
+            part[tid] += y;
+            __syncthreads();
+        }
+        uint64_t run = tid ? part[tid - 1] : 0ull;
+        for (uint32_t e = 0; e < sper; e++) {
+            uint32_t j = tid * sper + e;
+            if (j < ns) {
+                start[j] = run;
+                run += items(j, q);
+            }
+        }
+        if (tid == 1023) {
+            start[ns] = part[1023];
+            l.cursor[q * kCursorStride] = 0;
+        }
+        __syncthreads();   // part[] is read above before the next queue's sums overwrite it
     }
-    if (tid == 1023) {
-        l.seg_start[ns] = part[1023];
-        *l.n_seg = ns;
-        *l.cursor = 0;
-    }
+    if (tid == 0) *l.n_seg = ns;
 }
 
 hipError_t launch_lds_plan(const LdsArgs& l, hipStream_t s) {
@@ -994,11 +1000,68 @@ __device__ __forceinline__ uint32_t locate_item(const uint64_t* start, uint32_t 
     }
 }
 
-// BATCHED: every stage of every rank from one queue. Wave 0 pops the next
-// item as soon as the current one starts, so the queue's round trip and the
-// segment search overlap with the stage's work. Dependencies point to earlier
-// items only, and the earliest unfinished item is always some workgroup's
-// current one, so holding one popped item ahead cannot deadlock.
+// Segment of queue item `item` with no hint: a 64-ary search, one coalesced
+// load of 64 evenly spaced segment starts per step (starts never decrease,
+// start[0] = 0 <= item < start[ns]).
+__device__ __forceinline__ uint32_t locate_far(const uint64_t* start, uint32_t ns, uint64_t item, uint64_t& first) {
+    const uint32_t lane = __lane_id();
+    uint32_t lo = 0, hi = ns;   // start[lo] <= item, and the answer is below hi
+    while (hi - lo > 64) {
+        const uint32_t step = (hi - lo + 63) / 64;
+        const uint32_t j = lo + lane * step;
+        const uint64_t v = j < hi ? start[j] : ~0ull;
+        const uint64_t m = __ballot(v <= item);   // a prefix of the lanes, lane 0 included
+        const uint32_t h = 63u - (uint32_t)__clzll(m);
+        const uint32_t nlo = lo + h * step;
+        if (nlo + step < hi) hi = nlo + step;
+        lo = nlo;
+    }
+    const uint32_t j = lo + lane;
+    const uint64_t v = j < hi ? start[j] : ~0ull;
+    const uint64_t m = __ballot(v <= item);
+    const uint32_t h = 63u - (uint32_t)__clzll(m);
+    first = __shfl(v, (int)h);
+    return lo + h;
+}
+
+// Wave 0: place item `it`, popped from queue q, in its segment; when it lies
+// past the end of q, pop the other queues in turn. Returns false once every
+// queue is exhausted (cursors only grow, so an exhausted queue stays so).
+// `near` says sg is the current segment of q, a valid search hint.
+__device__ __forceinline__ bool settle_item(const LdsArgs& l, uint32_t ns, uint32_t& q, uint64_t& it, uint32_t& sg,
+                                            uint64_t& first, bool near) {
+    const uint32_t NQ = l.n_queues;
+    const uint64_t* start = l.seg_start + (uint64_t)q * (ns + 1);
+    if (it < start[ns]) {
+        sg = near ? locate_item(start, ns, it, sg, first) : locate_far(start, ns, it, first);
+        return true;
+    }
+    for (uint32_t d = 1; d < NQ; d++) {
+        const uint32_t q2 = (q + d) % NQ;
+        const uint64_t* s2 = l.seg_start + (uint64_t)q2 * (ns + 1);
+        uint64_t v = 0;
+        if (__lane_id() == 0) v = add_dev(&l.cursor[q2 * kCursorStride], 1ull);
+        v = __shfl(v, 0);
+        if (v < s2[ns]) {
+            q = q2;
+            it = v;
+            sg = locate_far(s2, ns, v, first);
+            return true;
+        }
+    }
+    return false;
+}
+
+// BATCHED: every stage of every rank from per-XCD queues. A workgroup takes
+// the items of its own queue, then helps the others. Wave 0 pops the next item
+// of the current queue as soon as the current one starts, so the queue's round
+// trip and the segment search overlap with the stage's work.
+// No deadlock: dependencies point to items of earlier segments only. Take the
+// unfinished item X of the earliest segment, in queue q. If it runs, what it
+// waits for has finished. If it is held popped ahead, its holder runs an item
+// of q before it, which cannot depend on it. If it is not popped, every
+// workgroup of q (one at least: n_queues <= grid) runs an earlier item of q,
+// finished or independent of X, and then pops on towards X.
 template <int W, uint32_t B, bool PK>
 __global__ void __launch_bounds__(B, 4) k_lds_persistent(CountArgs a, LdsArgs l) {
     extern __shared__ __align__(16) uint8_t lds_raw[];
@@ -1006,33 +1069,37 @@ __global__ void __launch_bounds__(B, 4) k_lds_persistent(CountArgs a, LdsArgs l)
     uint64_t* s_item = (uint64_t*)(lds_raw + kLdsHist * 4);
     uint64_t* s_first = s_item + 1;
     uint32_t* s_seg = (uint32_t*)(s_item + 2);
+    uint32_t* s_q = s_seg + 1;   // current queue; n_queues once every queue is exhausted
     static_assert(kLdsHist * 4 + 24 <= kProbeHistAt && kProbeHistAt + 4 * kProbeHist <= kLdsReserved - 4,
                   "queue scalars and probe counts exceed the reserved LDS");
     const uint32_t tid = threadIdx.x;
     hist_begin<B>(l, s);
     uint32_t wmax = 0;
     const uint32_t ns = *l.n_seg;
-    const uint64_t total = l.seg_start[ns];
+    const uint32_t NQ = l.n_queues;
     const uint32_t L = l.lag;
     if (tid < 64) {
+        uint32_t q = blockIdx.x % NQ, sg = 0;
         uint64_t it = 0, first = 0;
-        if (tid == 0) it = add_dev(l.cursor, 1ull);
+        if (tid == 0) it = add_dev(&l.cursor[q * kCursorStride], 1ull);
         it = __shfl(it, 0);
-        const uint32_t sg = it < total ? locate_item(l.seg_start, ns, it, 0, first) : 0u;
+        const bool ok = settle_item(l, ns, q, it, sg, first, false);
         if (tid == 0) {
             *s_item = it;
             *s_first = first;
             *s_seg = sg;
+            *s_q = ok ? q : NQ;
         }
     }
     __syncthreads();
     for (;;) {
+        const uint32_t q = *s_q;
+        if (q >= NQ) break;
         const uint64_t item = *s_item;
-        if (item >= total) break;
         const uint32_t seg = *s_seg;
         const uint32_t local = (uint32_t)(item - *s_first);
         uint64_t nxt = 0;
-        if (tid == 0) nxt = add_dev(l.cursor, 1ull);   // waited for only after the stage
+        if (tid == 0) nxt = add_dev(&l.cursor[q * kCursorStride], 1ull);   // waited for only after the stage
         const uint32_t st = seg & 3, tick = seg >> 2;
         const uint32_t lagv = st == 0 ? 0u : st == 1 ? 1u : st == 2 ? 2u : 2u + L;
         const uint32_t r = tick - lagv;
@@ -1074,13 +1141,14 @@ __global__ void __launch_bounds__(B, 4) k_lds_persistent(CountArgs a, LdsArgs l)
             add_dev(&l.stage_clocks[4 + st], 1ull);
         }
         if (tid < 64) {
-            uint64_t first = 0;
-            const uint64_t it = __shfl(nxt, 0);
-            const uint32_t sg = it < total ? locate_item(l.seg_start, ns, it, seg, first) : seg;
+            uint32_t q2 = q, sg = seg;
+            uint64_t it = __shfl(nxt, 0), first = 0;
+            const bool ok = settle_item(l, ns, q2, it, sg, first, true);
             if (tid == 0) {
                 *s_item = it;
                 *s_first = first;
                 *s_seg = sg;
+                *s_q = ok ? q2 : NQ;
             }
         }
         __syncthreads();

@@ -40,7 +40,7 @@ std::vector<Candidate> candidates(const gerbil_params* p) {
     if (p->table != GERBIL_TABLE_HBM && (p->k + 31) / 32 <= GERBIL_MAX_LDS_W) {
         // LDS: one 1024-thread workgroup per CU, or two of 512 with half-size tables
         const float fills[] = {0.6f, 0.8f, 1.0f, 1.2f};
-        const uint32_t pools[] = {4, 8, 16};
+        const uint32_t pools[] = {8, 16, 24};   // multiples of the XCD queues
         for (uint32_t b : {1024u, 512u}) {
             if (!batched && b != 1024u) continue;
             for (float f : fills) {

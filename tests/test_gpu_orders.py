@@ -215,14 +215,17 @@ def _bit_length(x):
     return n + (y > 0)
 
 
-@pytest.mark.parametrize("k", [31, 65, 200])
-def test_hll_registers_equal_those_of_the_distinct_keys(k):
+@pytest.mark.parametrize("k,canonical", [(31, True), (64, True), (65, True), (96, True), (200, True),
+                                         (65, False), (96, False)])
+def test_hll_registers_equal_those_of_the_distinct_keys(k, canonical):
     """A register keeps a maximum, so the sketch of a bin's occurrences equals
     the sketch of its distinct keys: the registers from the super-mers must
-    match, exactly, registers built on the host from the emitted keys."""
-    a, o = sample_reads(3 * k, n=300, lo=k, hi=k + 500)
+    match, exactly, registers built on the host from the emitted keys. k = 64
+    and 96 fill the last key word (the rolling window shifts by 62 bits);
+    canonical=False hashes forward k-mers only (App. A)."""
+    a, o = sample_reads(3 * k + int(canonical), n=300, lo=k, hi=k + 500)
     nb, p = 16, 10
-    job = make_job(a, o, k, m=9, n_bins=nb, threshold=1, mode=g.GERBIL_BATCHED)
+    job = make_job(a, o, k, m=9, n_bins=nb, threshold=1, mode=g.GERBIL_BATCHED, canonical=canonical)
     job.run()
     res = job.result()
     n = res.counts.size
