@@ -108,7 +108,8 @@ class HipEvents:
 
 # Kernel sources whose change invalidates the measured HBM traffic of the counting kernel.
 TRAFFIC_SOURCES = ["paper_1607_06618_amd/csrc/lds.hip", "paper_1607_06618_amd/csrc/common.h",
-                   "paper_1607_06618_amd/csrc/internal.h", "paper_1607_06618_amd/csrc/table.h"]
+                   "paper_1607_06618_amd/csrc/internal.h", "paper_1607_06618_amd/csrc/table.h",
+                   "paper_1607_06618_amd/csrc/api.hip"]
 
 
 def sources_digest(paths) -> str:
@@ -138,6 +139,44 @@ def measured_traffic(kernel: str, workload: str):
         return int(float(vals["traffic_bytes"]))
     except (KeyError, ValueError):
         return None
+
+
+def hll_cardinality(regs):
+    """HyperLogLog estimate of each row of registers (Flajolet et al. 2007),
+    with linear counting while an estimate is small."""
+    import numpy as np
+    m = regs.shape[1]
+    alpha = 0.7213 / (1.0 + 1.079 / m)
+    est = alpha * m * m / np.exp2(-regs.astype(np.float64)).sum(axis=1)
+    zeros = (regs == 0).sum(axis=1)
+    small = (est <= 2.5 * m) & (zeros > 0)
+    est[small] = m * np.log(m / zeros[small])
+    return est
+
+
+def bin_diagnostics(job, stream) -> dict:
+    """The realised bins of a counted job: k-mer occurrences per bin (quantiles,
+    largest over median) and each bin's distinct fraction rho = distinct keys /
+    occurrences, its distinct keys estimated from a HyperLogLog sketch of the
+    bin (2^12 registers, about 1.6% standard error)."""
+    import numpy as np
+    import torch
+    from paper_1607_06618_amd import gerbil as g
+    nb = int(job.bins.n_bins)
+    off = int(job.bins.bin_kmers) - job.ws_bin.data_ptr()
+    km = job.ws_bin[off: off + 8 * nb].cpu().numpy().view(np.uint64).astype(np.float64)
+    with torch.cuda.stream(stream):
+        regs = g.hll_registers(job, 12, stream).cpu().numpy()
+    torch.cuda.synchronize()
+    used = km > 0
+    rho = hll_cardinality(regs)[used] / km[used]
+
+    def quant(x):
+        return {f"p{q}": float(f"{np.percentile(x, q):.6g}") for q in (0, 10, 50, 90, 99, 100)} if x.size else {}
+    med = float(np.median(km[used])) if used.any() else 0.0
+    return {"n_bins": nb, "empty_bins": int((~used).sum()), "kmers_per_bin": quant(km[used]),
+            "largest_over_median": round(float(km.max()) / med, 3) if med else None,
+            "rho_per_bin": quant(rho), "rho_from": "HyperLogLog per bin, 2^12 registers"}
 
 
 def calibrate_copy(nbytes: int) -> int:
@@ -355,6 +394,8 @@ def main(argv=None):
             torch.cuda.synchronize()
             wall = time.perf_counter() - wall0
             res_t = job.result()
+            if not graph and "bins" not in shared_out:
+                shared_out["bins"] = bin_diagnostics(job, stream)   # after the timed steps
             job.close()
         for s in range(args.steps):
             step_ms.append(starts[s].elapsed_time(starts[s + 1]))
@@ -453,6 +494,7 @@ def main(argv=None):
         "cpu_baseline": cpu,
         "p50_ms": percentile(R["step_ms"], 50), "p99_ms": percentile(R["step_ms"], 99),
         "checks": checks,
+        "bins": shared_out.get("bins"),
     }
     for m, r in results.items():
         out[f"{m}_kmers_per_s"] = n_valid * args.steps / r["wall"]
