@@ -91,6 +91,9 @@ class Result:
         return self.keys[order], self.counts[order]
 
 
+SERVING_KEY_SLOTS = 8
+
+
 def footprint(n_bytes: int, n_reads: int, k: int, m: int, n_bins: int, threshold: int) -> int:
     """Estimated device bytes of one job (admission control)."""
     W = (k + 31) // 32
@@ -99,7 +102,7 @@ def footprint(n_bytes: int, n_reads: int, k: int, m: int, n_bins: int, threshold
     enc = n_bytes // 4 + 3 * (n_bytes // 8) + 4096
     superm = min(n_bytes, n_bytes * 4 // (w + 1) + n_bytes // 2048 + 4096)
     bins = superm * 20 + n_bins * 32
-    keys = 8 * 2 * n_bytes * 8 * W // max(1, n_bins) + (1 << 24)      # key slots, bins up to 2x the mean
+    keys = SERVING_KEY_SLOTS * 2 * n_bytes * 8 * W // max(1, n_bins) + (1 << 24)   # key slots, bins up to 2x the mean
     out = (n_bytes // (2 * threshold) + 1) * (8 * W + 4)               # first output guess
     return ascii_b + enc + bins + keys + out + (1 << 22)
 
@@ -178,7 +181,10 @@ class _Job:
             self.ascii_d = torch.as_tensor(req.ascii).to(device, non_blocking=True)
             self.offsets_d = torch.as_tensor(req.offsets).to(device, non_blocking=True)
             n_bytes = int(self.ascii_d.numel())
-            p = g.make_params(req.k, req.m, req.n_bins, req.threshold, mode=g.GERBIL_BATCHED)
+            # 8 key slots (one per XCD queue) instead of the library's 16: the jobs in
+            # flight already overlap on the GPU, and a smaller count workspace per job
+            # keeps the allocator's cache of freed workspaces small
+            p = g.make_params(req.k, req.m, req.n_bins, req.threshold, mode=g.GERBIL_BATCHED, pool=SERVING_KEY_SLOTS)
             if params_hook is not None:
                 params_hook(p)
             import ctypes
