@@ -18,6 +18,15 @@
 #define GERBIL_MAX_LDS_W 8      // LDS tables: keys of up to 8 words (k <= 256)
 #define GERBIL_EMPTY (~(uint64_t)0)    // probe word of an unclaimed slot
 
+// Keys of k >= 32 counted as read (the `-d` mode of App. A) are stored with
+// their first word XORed with this constant, and the XOR is undone on output. The all-T
+// prefix (an all-ones word, the empty-slot marker), common in real reads as
+// poly-A/poly-T tracts, is then an ordinary key; the stored word that equals
+// the marker belongs to one fixed, irregular 32-mer, whose occurrences take
+// the emergency area. Canonical keys are stored unchanged: a canonical key
+// starts with 32 T's only if its reverse complement does too.
+#define GERBIL_DIRECT_XOR 0x9E3779B97F4A7C15ull
+
 // Device status bits (written with atomicOr, read back by the host).
 #define ST_OUT_CAP 0x1u         // output pairs exceeded the caller's capacity
 #define ST_OVF_CAP 0x2u         // emergency area exceeded its capacity
@@ -63,6 +72,14 @@ __device__ __forceinline__ void extract_kmer(const uint64_t* __restrict__ P, int
     fw[W - 1] = sh ? (tail >> sh) : tail;
     uint64_t rtail = revcomp32(window32(P, p - 32 + (int64_t)r));
     rc[W - 1] = sh ? (rtail >> sh) : rtail;
+}
+
+// XOR applied to a key's first word in the tables (GERBIL_DIRECT_XOR). Below
+// k = 32 the one key word holds 2k bits under zero top bits, so it never
+// equals the marker, and it is kept as is: the LDS path stores a key's last
+// word in only as many bytes as its bases need.
+__device__ __forceinline__ uint64_t stored_xor(uint32_t canonical, uint32_t k) {
+    return canonical || k < 32 ? 0ull : GERBIL_DIRECT_XOR;
 }
 
 // canonical = lexicographically smaller of fw and rc (compare from word 0);

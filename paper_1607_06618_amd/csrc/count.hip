@@ -153,7 +153,7 @@ __global__ void __launch_bounds__(kOvfBlock) k_ovf_dump(CountArgs a) {
             if (pos < a.cap) {
                 const uint64_t* key = a.ovf_keys + (uint64_t)(rep - 1) * W;
 #pragma unroll
-                for (int w = 0; w < W; w++) a.out_keys[pos * W + w] = key[w];
+                for (int w = 0; w < W; w++) a.out_keys[pos * W + w] = key[w] ^ (w ? 0ull : stored_xor(a.canonical, a.k));
                 a.out_counts[pos] = c;
             } else {
                 set_status(a.status, ST_OUT_CAP);

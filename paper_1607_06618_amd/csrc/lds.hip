@@ -499,6 +499,7 @@ __device__ __forceinline__ ChunkLds chunk_lds(const Lds& s) {
 template <int W, uint32_t B>
 __device__ void stage_count(const CountArgs& a, const LdsArgs& l, const Lds& s, uint32_t r, uint32_t chunk) {
     const uint32_t tid = threadIdx.x;
+    const uint64_t kx = stored_xor(a.canonical, a.k);
     const uint32_t b = l.rank_bin[r], v = l.rank_slice[r], V = l.rank_nslice[r], P = l.rank_nsub[r];
     const ChunkLds c = chunk_lds<B>(s);
     static_assert(chunk_header<B>() + 4 * LdsShape<B>::max_sub <= LdsShape<B>::bytes - kLdsReserved,
@@ -516,6 +517,7 @@ __device__ void stage_count(const CountArgs& a, const LdsArgs& l, const Lds& s, 
             if (j) seg_step<W>(a.k, g);
             uint64_t key[W];
             canonical_of<W>(g.fw, g.rc, key, a.canonical);
+            key[0] ^= kx;
             const uint64_t h = key_hash<W>(key, a.seed);
             if (V > 1 && slice_of(h, V) != v) continue;
             atomicAdd(&hist[sub_of(h, P)], 1u);
@@ -576,6 +578,7 @@ template <int W, uint32_t B>
 __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s, uint32_t r, uint32_t chunk) {
     constexpr int R = ScatterRound<W>::R;
     const uint32_t tid = threadIdx.x;
+    const uint64_t kx = stored_xor(a.canonical, a.k);
     const uint32_t b = l.rank_bin[r], v = l.rank_slice[r], V = l.rank_nslice[r], P = l.rank_nsub[r];
     const uint64_t sb = l.rank_spbase[r];
     uint64_t* slot = l.keys + (uint64_t)(r % l.Q) * l.slot_words;
@@ -618,6 +621,7 @@ __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s
                     if ((uint32_t)e < g.len) {
                         if (e) seg_step<W>(a.k, g);
                         canonical_of<W>(g.fw, g.rc, key[e], a.canonical);
+                        key[e][0] ^= kx;
                         const uint64_t h = key_hash<W>(key[e], a.seed);
                         if (V == 1 || slice_of(h, V) == v) {
                             sp[e] = sub_of(h, P);
@@ -710,8 +714,8 @@ __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s
 // counter found non-zero guarantees that the words read after it are the
 // slot's key. A slot found claimed but not yet published, or lost to
 // another claimer, is probed again in the next iteration. Keys whose theta
-// probes fail, and keys whose first word is the empty-slot marker (an all-T
-// word, never stored), go to the emergency area.
+// probes fail, and keys whose stored first word is the empty-slot marker
+// (never stored), go to the emergency area.
 //
 // Slot layouts (PK): unpacked, probe words w0[C], the other words rest[(W-1) C]
 // and 32-bit counters cnt[C]; packed (W >= 2 and a last word of at most 16
@@ -934,7 +938,7 @@ __device__ void stage_table(const CountArgs& a, const LdsArgs& l, const Lds& s, 
         const uint32_t c = count_at(sl);
         if (c && c >= a.threshold) {
             if (pos < a.cap) {
-                a.out_keys[pos * W] = w0[sl];
+                a.out_keys[pos * W] = w0[sl] ^ stored_xor(a.canonical, a.k);
                 if (PK) {
 #pragma unroll
                     for (int i = 1; i + 1 < W; i++) a.out_keys[pos * W + i] = rest[(uint32_t)(i - 1) * C + sl];

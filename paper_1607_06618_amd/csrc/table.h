@@ -15,9 +15,12 @@
 //     apart from the rest of the key, structure of arrays);
 //   * trial t probes bucket (b0 + t*s) mod nb with nb a power of two and s odd
 //     (double hashing with a full period);
-//   * a slot is claimed by CAS on word 0 (EMPTY = all ones, 32 T's). A key
-//     whose word 0 is all ones takes the emergency path instead: a canonical
-//     key can have one only when k >= 64, a `-d` key whenever k >= 32. For W >= 2 the claimer then stores words 1..W-1 and
+//   * a slot is claimed by CAS on word 0 (EMPTY = all ones). A key whose
+//     stored word 0 is all ones takes the emergency path instead: a canonical
+//     key (stored as is) has one only when it starts with 32 T's and k >= 64,
+//     a `-d` key (word 0 stored XORed with GERBIL_DIRECT_XOR) only when it
+//     starts with the one 32-mer that the XOR maps onto the marker. For W >= 2
+//     the claimer then stores words 1..W-1 and
 //     publishes the key by raising the counter from 0 to 1; a lane that finds
 //     its word 0 in a claimed slot waits until the counter is non-zero before
 //     comparing the other words. Claim, store and publish happen in one loop
@@ -64,7 +67,7 @@ __device__ __forceinline__ void overflow_push(const CountArgs& a, const uint64_t
 template <int W>
 __device__ __forceinline__ bool table_insert(const CountArgs& a, const Table& t, uint32_t nb,
                                              const uint64_t (&key)[W], uint64_t h) {
-    if (key[0] == GERBIL_EMPTY) return false;   // the empty-slot marker (an all-T word) is never stored
+    if (key[0] == GERBIL_EMPTY) return false;   // the empty-slot marker is never stored
     // nb is a power of two and the step is odd: the theta buckets are distinct
     const uint32_t mask = nb - 1;
     const uint32_t step = ((uint32_t)(h >> 32) | 1u) & mask | 1u;
@@ -171,7 +174,7 @@ __device__ __forceinline__ void compact_slot(const CountArgs& a, const Table& t,
     uint64_t pos = wave_reserve(a.n_out, emit);
     if (emit) {
         if (pos < a.cap) {
-            a.out_keys[pos * W] = ld_dev(t.w0 + slot);
+            a.out_keys[pos * W] = ld_dev(t.w0 + slot) ^ stored_xor(a.canonical, a.k);
 #pragma unroll
             for (int i = 1; i < W; i++) a.out_keys[pos * W + i] = load_rest(t.rest + (uint64_t)(i - 1) * t.stride + slot);
             a.out_counts[pos] = c;
@@ -206,6 +209,7 @@ __device__ __forceinline__ void count_position(const CountArgs& a, const Table& 
     uint64_t fw[W], rc[W], key[W];
     extract_kmer<W>(a.packed, p, a.k, fw, rc);
     canonical_of<W>(fw, rc, key, a.canonical);
+    key[0] ^= stored_xor(a.canonical, a.k);
     uint64_t h = key_hash<W>(key, a.seed);
     if (!table_insert<W>(a, t, nb, key, h)) overflow_push<W>(a, key);
 }

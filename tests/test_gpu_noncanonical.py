@@ -3,8 +3,10 @@ normalisation, against the oracle's non-canonical count, element by element.
 
 A k-mer and its reverse complement are then two keys, so the key that is all
 T's (at k = 32) and keys whose first word is 32 T's (k >= 64), which a
-canonical count never or rarely meets, occur here and must take the
-emergency area (the all-ones word marks an empty table slot).
+canonical count never or rarely meets, occur here. The all-ones word marks an
+empty table slot, so in this mode a key's first word is stored XORed with a
+fixed constant: poly-T keys are counted in the tables, and the keys that start
+with the one 32-mer the XOR maps onto the marker take the emergency area.
 """
 import numpy as np
 import pytest
@@ -65,18 +67,41 @@ def test_noncanonical_parity_random(k, t, table, mode):
     compare_d(a, o, k, min(9, k - 1), 37, t, hist_len=64, table=table, mode=mode)
 
 
+# the 32-mer whose first word, XORed with the stored-key constant of the
+# `-d` mode (0x9E3779B97F4A7C15), is the all-ones empty-slot marker
+MARKER_32MER = oracle.decode_key(np.array([~np.uint64(0x9E3779B97F4A7C15)], dtype=np.uint64), 32)
+
+
 @pytest.mark.parametrize("k", [32, 64, 96])
 @pytest.mark.parametrize("table", TABLES)
 @pytest.mark.parametrize("mode", MODES)
-def test_all_t_keys_take_the_emergency_area(k, table, mode):
+def test_all_t_keys_are_counted_in_the_tables(k, table, mode):
     reads = ["T" * 300, "A" * 300, "T" * 40 + "ACGGT" * 30, "CA" + "T" * 120] * 10 + ["ACGTTGCA" * 30] * 5
     a, o = reads_to_csr(reads)
-    res, ref = compare_d(a, o, k, 9, 8, 1, expect_overflow=True, table=table, mode=mode)
+    res, ref = compare_d(a, o, k, 9, 8, 1, table=table, mode=mode)
+    assert res.report.n_overflow == 0
     # the all-T k-mer and the all-A k-mer are two keys here
     words = g.words(k)
     all_t = [(1 << 64) - 1] * (words - 1) + [(1 << (2 * (k - 32 * (words - 1)))) - 1]
     hit = np.nonzero((res.sorted()[0] == np.array(all_t, dtype=np.uint64)).all(axis=1))[0]
     assert hit.size == 1
+    assert int(res.sorted()[1][hit[0]]) == 10 * (300 - k + 1) + 10 * (120 - k + 1) + 10 * max(0, 40 - k + 1)
+
+
+@pytest.mark.parametrize("k", [32, 64, 96])
+@pytest.mark.parametrize("table", TABLES)
+@pytest.mark.parametrize("mode", MODES)
+def test_keys_stored_as_the_marker_take_the_emergency_area(k, table, mode):
+    assert len(MARKER_32MER) == 32 and set(MARKER_32MER) <= set("ACGT")
+    rng = np.random.default_rng(77 + k)
+    tail = lambda n: "".join(np.array(list("ACGT"))[rng.integers(0, 4, n)].tolist())
+    reads = ([MARKER_32MER + tail(150), tail(7) + MARKER_32MER + tail(120), MARKER_32MER * 3 + tail(40)] * 6
+             + [tail(200) for _ in range(20)])
+    a, o = reads_to_csr(reads)
+    res, ref = compare_d(a, o, k, 9, 8, 1, expect_overflow=True, table=table, mode=mode)
+    keys = res.sorted()[0]
+    first = np.array([oracle.decode_key(kk, k)[:32] for kk in keys])
+    assert (first == MARKER_32MER).sum() >= (1 if k == 32 else 3)   # at k = 32 the marker 32-mer is one key
 
 
 @pytest.mark.parametrize("mode", MODES)
