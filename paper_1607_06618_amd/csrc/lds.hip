@@ -574,8 +574,9 @@ __device__ void stage_scan(const CountArgs& a, const LdsArgs& l, const Lds& s, u
 // every thread takes one segment of up to R k-mers (keys held in registers);
 // the round's keys are grouped by sub-table in LDS, one global reservation is
 // made per sub-table, and each run is written as consecutive words.
-template <int W, uint32_t B, int R, uint32_t PMAX>
-__device__ void stage_scatter_r(const CountArgs& a, const LdsArgs& l, const Lds& s, uint32_t r, uint32_t chunk) {
+template <int W, uint32_t B>
+__device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s, uint32_t r, uint32_t chunk) {
+    constexpr int R = ScatterRound<W>::R;
     const uint32_t tid = threadIdx.x;
     const uint64_t kx = stored_xor(a.canonical, a.k);
     const uint32_t b = l.rank_bin[r], v = l.rank_slice[r], V = l.rank_nslice[r], P = l.rank_nsub[r];
@@ -583,12 +584,12 @@ __device__ void stage_scatter_r(const CountArgs& a, const LdsArgs& l, const Lds&
     uint64_t* slot = l.keys + (uint64_t)(r % l.Q) * l.slot_words;
     uint8_t* tail = (uint8_t*)(slot + (uint64_t)(W - 1) * l.slot_keys);
     const ChunkLds c = chunk_lds<B>(s);
-    static_assert(chunk_header<B>() + 3 * 4 * PMAX + (uint64_t)R * 8 * W * B <= LdsShape<B>::bytes - kLdsReserved,
+    static_assert(chunk_header<B>() + 3 * 4 * LdsShape<B>::max_sub + (uint64_t)R * 8 * W * B <= LdsShape<B>::bytes - kLdsReserved,
                   "scatter stage exceeds the LDS budget");
     uint32_t* cnt = (uint32_t*)c.rest;
-    uint32_t* lp = cnt + PMAX;
-    uint32_t* dst = lp + PMAX;   // run start of this round, relative to the key slot
-    uint64_t* buf = (uint64_t*)(dst + PMAX);
+    uint32_t* lp = cnt + LdsShape<B>::max_sub;
+    uint32_t* dst = lp + LdsShape<B>::max_sub;   // run start of this round, relative to the key slot
+    uint64_t* buf = (uint64_t*)(dst + LdsShape<B>::max_sub);
     for (uint32_t j = tid; j < P; j += B) cnt[j] = 0;
     const uint32_t S = load_chunk_seg<B>(a, l, b, chunk, R, c.sdesc, c.sgpre, c.wsum);
     const uint32_t rounds = (S + B - 1) / B;
@@ -700,22 +701,6 @@ __device__ void stage_scatter_r(const CountArgs& a, const LdsArgs& l, const Lds&
         for (uint32_t j = tid; j < P; j += B) cnt[j] = 0;
         __syncthreads();   // counts cleared before the next round adds to them
     }
-}
-
-// Ranks of at most kWideP sub-tables leave LDS for one more key per thread
-// and round at W = 3 (fewer rounds, and more keys per run and round).
-constexpr uint32_t kWideP = 2048;
-template <int W, uint32_t B>
-__device__ __forceinline__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s, uint32_t r,
-                                              uint32_t chunk) {
-    constexpr int R = ScatterRound<W>::R;
-    if constexpr (W == 3 && B == 1024) {
-        if (l.rank_nsub[r] <= kWideP) {
-            stage_scatter_r<W, B, R + 1, kWideP>(a, l, s, r, chunk);
-            return;
-        }
-    }
-    stage_scatter_r<W, B, R, LdsShape<B>::max_sub>(a, l, s, r, chunk);
 }
 
 // Alg. 1 in an LDS table of C slots (structure of arrays) for the K keys a
