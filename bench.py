@@ -314,8 +314,8 @@ def device_ceilings():
 def main(argv=None):
     args = parse_args(argv)
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              f"(the multi-GPU sharding is a design note only)", file=sys.stderr, flush=True)
+        print(f"bench.py: the counting path runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(sharding over several GPUs is described, not built)", file=sys.stderr, flush=True)
         return 2
 
     if args.calibrate_copy:

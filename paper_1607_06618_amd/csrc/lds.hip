@@ -593,8 +593,6 @@ __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s
     for (uint32_t j = tid; j < P; j += B) cnt[j] = 0;
     const uint32_t S = load_chunk_seg<B>(a, l, b, chunk, R, c.sdesc, c.sgpre, c.wsum);
     const uint32_t rounds = (S + B - 1) / B;
-    // the segment of the next round is opened (its packed words requested)
-    // while the current round is written out
     // For short keys the next round's words are fetched while this round is
     // written out; longer keys (more registers per key) open at round start.
     constexpr bool kAhead = W <= 3;
