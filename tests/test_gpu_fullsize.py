@@ -53,7 +53,7 @@ def check_against_golden(name, job, gold, W, k):
 
 
 @pytest.mark.parametrize("name,tune,block", [("c2_k65", False, 0), ("c2_k65", False, 512), ("c3_skew", True, 0),
-                                              ("c4_longk", False, 0)])
+                                              ("c3_skew", False, 0), ("c4_longk", False, 0), ("c4_longk", False, 512)])
 def test_full_size_workload(name, tune, block):
     import torch
     if not os.path.exists(fullsize.golden_path(name)):
