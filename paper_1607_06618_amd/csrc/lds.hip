@@ -596,6 +596,11 @@ __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s
     // For short keys the next round's words are fetched while this round is
     // written out; longer keys (more registers per key) open at round start.
     constexpr bool kAhead = W <= 3;
+    // A last key word of at most 16 bases (2r <= 32 bits) carries the key's
+    // sub-table in its top 16 bits while it is staged in LDS, so the store
+    // loop reads the sub-table of a sorted position instead of searching lp[].
+    const bool tagged = a.k - 32u * (W - 1) <= 16u;
+    constexpr uint64_t kTagMask = (1ull << 48) - 1;
     SegRaw<W> raw;
     raw.ok = false;
     if (kAhead && tid < S) seg_fetch<W, B>(a, c.sdesc, c.sgpre, tid, R, raw);
@@ -646,7 +651,8 @@ __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s
             if (sp[e] == kNone) continue;
             const uint32_t pos = lp[sp[e]] + rk[e];
 #pragma unroll
-            for (int w = 0; w < W; w++) buf[(uint64_t)pos * W + w] = key[e][w];
+            for (int w = 0; w + 1 < W; w++) buf[(uint64_t)pos * W + w] = key[e][w];
+            buf[(uint64_t)pos * W + W - 1] = tagged ? key[e][W - 1] | ((uint64_t)sp[e] << 48) : key[e][W - 1];
         }
         if (kAhead) {
             raw.ok = false;
@@ -657,10 +663,16 @@ __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s
         // atomic here would make every iteration wait for all earlier stores)
         uint32_t spilled = 0;
         for (uint32_t i = tid; i < T; i += B) {
-            uint32_t lo = 0, hi = P;   // last sub-table whose run starts at or before i
-            while (hi - lo > 1) {
-                uint32_t mid = (lo + hi) >> 1;
-                if (lp[mid] <= i) lo = mid; else hi = mid;
+            const uint64_t lw = buf[(uint64_t)i * W + W - 1];
+            uint32_t lo = 0;   // sub-table of sorted position i
+            if (tagged) {
+                lo = (uint32_t)(lw >> 48);
+            } else {
+                uint32_t hi = P;   // last sub-table whose run starts at or before i
+                while (hi - lo > 1) {
+                    uint32_t mid = (lo + hi) >> 1;
+                    if (lp[mid] <= i) lo = mid; else hi = mid;
+                }
             }
             const uint32_t q = i - lp[lo];
             if (q < cnt[lo]) {
@@ -671,7 +683,7 @@ __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s
 #pragma unroll
                     for (int w = 0; w + 1 < W; w++)
                         slot[(uint64_t)w * l.slot_keys + gpos] = buf[(uint64_t)i * W + w];
-                    store_tail(tail, gpos, buf[(uint64_t)i * W + W - 1], l.tail_bytes);
+                    store_tail(tail, gpos, tagged ? lw & kTagMask : lw, l.tail_bytes);
                 } else {
                     set_status(a.status, ST_POOL);
                 }
@@ -682,15 +694,22 @@ __device__ void stage_scatter(const CountArgs& a, const LdsArgs& l, const Lds& s
         // keys past the end of their run (runs are sized from a sample): emergency area
         if (block_any(spilled != 0, s.flag)) {
             for (uint32_t i = tid; i < T; i += B) {
-                uint32_t lo = 0, hi = P;
-                while (hi - lo > 1) {
-                    uint32_t mid = (lo + hi) >> 1;
-                    if (lp[mid] <= i) lo = mid; else hi = mid;
+                const uint64_t lw = buf[(uint64_t)i * W + W - 1];
+                uint32_t lo = 0;
+                if (tagged) {
+                    lo = (uint32_t)(lw >> 48);
+                } else {
+                    uint32_t hi = P;
+                    while (hi - lo > 1) {
+                        uint32_t mid = (lo + hi) >> 1;
+                        if (lp[mid] <= i) lo = mid; else hi = mid;
+                    }
                 }
                 if (i - lp[lo] < cnt[lo]) continue;
                 uint64_t key[W];
 #pragma unroll
-                for (int w = 0; w < W; w++) key[w] = buf[(uint64_t)i * W + w];
+                for (int w = 0; w + 1 < W; w++) key[w] = buf[(uint64_t)i * W + w];
+                key[W - 1] = tagged ? lw & kTagMask : lw;
                 overflow_push<W>(a, key);
                 if (l.probe_hist) atomicAdd(&s.probes[0], 1u);
             }
