@@ -3,8 +3,8 @@
 // open-addressing hash table with double hashing (Sec. 2.2, Alg. 1): a key
 // that matches a slot increments its counter, an empty slot takes the key
 // with count 1, otherwise the next trial is probed; after theta trials the
-// key goes to the emergency area (Sec. 3.4.3), which is sorted and
-// run-length counted after the tables. Tables are dumped after their bin
+// key goes to the emergency area (Sec. 3.4.3), counted after the tables in
+// a table of its own. Tables are dumped after their bin
 // (Sec. 2.3.2 step 3): pairs with count >= threshold are emitted (App. A
 // `-l`) and every count feeds the count-of-counts histogram.
 //
