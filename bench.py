@@ -554,7 +554,8 @@ def main(argv=None):
         for r in results.values():
             r["job"] = None
         shared_out.clear()
-        R = None
+        R = job = None   # the timing loop's last job holds its workspaces and outputs
+        torch.cuda.synchronize()
         torch.cuda.empty_cache()
         out["estimator"] = run_estimator(args, w, ascii_d, offsets_d, int(offsets[-1]), stream, cap=n_distinct + 1)
     if args.parse:
@@ -659,7 +660,9 @@ def run_estimator(args, w, ascii_d, offsets_d, n_bytes, stream, cap=None):
     from paper_1607_06618_amd import gerbil as g
 
     with torch.cuda.stream(stream):
-        p = g.make_params(w.k, w.m, w.n_bins, 1, mode=g.GERBIL_BATCHED, canonical=not args.non_canonical)
+        # threshold 1 keeps every distinct key (131 GB of keys on the skewed k = 99 reads); this
+        # count is not timed, so it takes 8 key slots, each sized for the largest bin, not 16
+        p = g.make_params(w.k, w.m, w.n_bins, 1, mode=g.GERBIL_BATCHED, canonical=not args.non_canonical, pool=8)
         job = g.Job(ascii_d, offsets_d, n_bytes, p, hist_len=65536, stream=stream, cap=cap)
         job.run()
         st, rep = g.gerbil_result(job.enc, job.bins, job.state, g._stream_handle(stream))
