@@ -115,7 +115,13 @@ __device__ __forceinline__ uint64_t pair_base(uint64_t w0, uint64_t w1, uint32_t
 template <uint32_t MW>
 __global__ void __launch_bounds__(kBinBlock, 7) k_bin_tiles(BinArgs a) {
     constexpr uint32_t kRankPer = rank_per<MW>();
+    // When a thread's run of ranks is one block of kMinPer positions, it also
+    // writes the block's minimum, and a window's middle part is read as block
+    // minima plus the ranks at its two ends.
+    constexpr bool kBlockMin = kRankPer == kMinPer;
+    constexpr uint32_t kBlocks = kBlockMin ? rank_len<MW>() / kMinPer : 1;
     __shared__ uint32_t R[rank_len<MW>()];
+    __shared__ uint32_t BM[kBlocks];   // BM[j] = min R[j*kMinPer .. (j+1)*kMinPer), whole blocks below len
     __shared__ uint32_t M[kTile + 1];
     __shared__ uint64_t brk[kWordsPerTile];
     __shared__ uint64_t stw[kWordsPerTile];
@@ -159,6 +165,7 @@ __global__ void __launch_bounds__(kBinBlock, 7) k_bin_tiles(BinArgs a) {
                 nb = win << (2 * a.m);
             }
             const int64_t n_left = (int64_t)n_pos - (P0 - 1 + (int64_t)i0);   // positions of this run in range
+            uint32_t bmin = 0xFFFFFFFFu;
             for (uint32_t i = i0; i < i1; i++) {
                 if (i > i0) {
                     const uint32_t b2 = (uint32_t)(nb >> 62);
@@ -166,8 +173,12 @@ __global__ void __launch_bounds__(kBinBlock, 7) k_bin_tiles(BinArgs a) {
                     fw = ((fw << 2) | b2) & code_mask;
                     rc = (rc >> 2) | ((3u - b2) << (2 * a.m - 2));
                 }
-                R[i] = (int64_t)(i - i0) < n_left ? rank_of32(fw, rc, a.m, a.order, a.rank_table) : 0xFFFFFFFFu;
+                const uint32_t rk = (int64_t)(i - i0) < n_left ? rank_of32(fw, rc, a.m, a.order, a.rank_table)
+                                                               : 0xFFFFFFFFu;
+                R[i] = rk;
+                bmin = min(bmin, rk);
             }
+            if (kBlockMin && i0 + kMinPer <= len) BM[tid] = bmin;   // a whole block: i0 = tid * kMinPer
             if (tid < kWordsPerTile) okS[tid] = f.ok;
         }
         // the next tile's loads are in flight while this one is processed
@@ -188,8 +199,17 @@ __global__ void __launch_bounds__(kBinBlock, 7) k_bin_tiles(BinArgs a) {
                 } else {
                     // window [i, i+w) = [i, i1-1) + [i1-1, i0+w) + [i0+w, i+w)
                     uint32_t mid = 0xFFFFFFFFu;
+                    const uint32_t lo = i1 - 1, hi = i0 + w;   // hi <= kTile + w = len
+                    const uint32_t jb = (lo + kMinPer - 1) / kMinPer, je = hi / kMinPer;
+                    if (kBlockMin && jb < je) {
+                        // whole blocks jb .. je-1 lie in [lo, hi) and below len
+                        for (uint32_t t = lo; t < jb * kMinPer; t++) mid = min(mid, R[t]);
+                        for (uint32_t j = jb; j < je; j++) mid = min(mid, BM[j]);
+                        for (uint32_t t = je * kMinPer; t < hi; t++) mid = min(mid, R[t]);
+                    } else {
 #pragma unroll 8
-                    for (uint32_t t = i1 - 1; t < i0 + w; t++) mid = min(mid, R[t]);
+                        for (uint32_t t = lo; t < hi; t++) mid = min(mid, R[t]);
+                    }
                     uint32_t suf[kMinPer], pre[kMinPer];
                     uint32_t run = 0xFFFFFFFFu;
 #pragma unroll
