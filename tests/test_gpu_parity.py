@@ -110,7 +110,11 @@ def oracle_pieces(a, o, k, m, nb, order, tile, bin_map=None):
 
 
 @pytest.mark.parametrize("k,m,nb,order", [(15, 5, 7, 0), (32, 7, 64, 0), (33, 9, 17, 1), (65, 9, 512, 0),
-                                          (99, 9, 33, 0), (200, 11, 2048, 0), (4, 3, 4, 1), (21, 15, 4096, 1)])
+                                          (99, 9, 33, 0), (200, 11, 2048, 0), (4, 3, 4, 1), (21, 15, 4096, 1),
+                                          # windows of w = k - m + 1 = 19, 27, 256 and 257 ranks: the shortest
+                                          # and a ragged window read through 9-rank block minima, the longest
+                                          # window of the short-window kernel, the shortest of the long one
+                                          (27, 9, 16, 1), (35, 9, 32, 0), (264, 9, 64, 0), (265, 9, 64, 0)])
 def test_bin_parity(k, m, nb, order):
     rng = np.random.default_rng(k * 31 + m)
     reads = random_reads(rng, 150, 0, 600, n_rate=0.005, junk="N") + ["ACGT" * 600, "A" * 3000]
