@@ -164,19 +164,23 @@ __global__ void __launch_bounds__(kBinBlock, 7) k_bin_tiles(BinArgs a) {
                 rc = (uint32_t)(revcomp32(win) & mmask);
                 nb = win << (2 * a.m);
             }
-            const int64_t n_left = (int64_t)n_pos - (P0 - 1 + (int64_t)i0);   // positions of this run in range
+            // positions of this run inside the read stream, at most kRankPer
+            const int64_t n_left = (int64_t)n_pos - (P0 - 1 + (int64_t)i0);
+            const uint32_t n_in = n_left <= 0 ? 0u : n_left >= (int64_t)kRankPer ? kRankPer : (uint32_t)n_left;
             uint32_t bmin = 0xFFFFFFFFu;
-            for (uint32_t i = i0; i < i1; i++) {
-                if (i > i0) {
-                    const uint32_t b2 = (uint32_t)(nb >> 62);
-                    nb <<= 2;
-                    fw = ((fw << 2) | b2) & code_mask;
-                    rc = (rc >> 2) | ((3u - b2) << (2 * a.m - 2));
+#pragma unroll
+            for (uint32_t e = 0; e < kRankPer; e++) {
+                if (i0 + e < i1) {
+                    if (e > 0) {
+                        const uint32_t b2 = (uint32_t)(nb >> 62);
+                        nb <<= 2;
+                        fw = ((fw << 2) | b2) & code_mask;
+                        rc = (rc >> 2) | ((3u - b2) << (2 * a.m - 2));
+                    }
+                    const uint32_t rk = e < n_in ? rank_of32(fw, rc, a.m, a.order, a.rank_table) : 0xFFFFFFFFu;
+                    R[i0 + e] = rk;
+                    bmin = min(bmin, rk);
                 }
-                const uint32_t rk = (int64_t)(i - i0) < n_left ? rank_of32(fw, rc, a.m, a.order, a.rank_table)
-                                                               : 0xFFFFFFFFu;
-                R[i] = rk;
-                bmin = min(bmin, rk);
             }
             if (kBlockMin && i0 + kMinPer <= len) BM[tid] = bmin;   // a whole block: i0 = tid * kMinPer
             if (tid < kWordsPerTile) okS[tid] = f.ok;
