@@ -182,7 +182,9 @@ __global__ void __launch_bounds__(kBinBlock, 7) k_bin_tiles(BinArgs a) {
                     bmin = min(bmin, rk);
                 }
             }
-            if (kBlockMin && i0 + kMinPer <= len) BM[tid] = bmin;   // a whole block: i0 = tid * kMinPer
+            if constexpr (kBlockMin) {
+                if (i0 + kMinPer <= len) BM[tid] = bmin;   // a whole block: i0 = tid * kMinPer
+            }
             if (tid < kWordsPerTile) okS[tid] = f.ok;
         }
         // the next tile's loads are in flight while this one is processed
