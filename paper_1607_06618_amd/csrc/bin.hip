@@ -376,10 +376,13 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_scatter(BinArgs a) {
     uint32_t* lh = sh;                  // [n_bins] counts in this chunk
     uint32_t* lk = sh + a.n_bins;       // [n_bins] k-mers in this chunk
     uint32_t* gb = sh + 2 * a.n_bins;   // [n_bins] global base of this chunk in the bin
+    // [n_bins] k-mers of this workgroup's chunks, added to the bins' totals once at the end
+    uint64_t* tk = (uint64_t*)(sh + 3 * a.n_bins + (a.n_bins & 1u));
     const uint32_t tid = threadIdx.x;
     uint64_t n = ld_dev(a.list_used);   // list slots handed out, holes included
     if (n > a.list_cap) n = a.list_cap;
     const uint64_t chunk = (uint64_t)kBinBlock * kScatterPer;
+    for (uint32_t b = tid; b < a.n_bins; b += kBinBlock) tk[b] = 0;   // read back only by thread b % kBinBlock
     for (uint64_t c0 = blockIdx.x * chunk; c0 < n; c0 += (uint64_t)gridDim.x * chunk) {
         for (uint32_t b = tid; b < a.n_bins; b += kBinBlock) { lh[b] = 0; lk[b] = 0; }
         __syncthreads();
@@ -404,7 +407,7 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_scatter(BinArgs a) {
         for (uint32_t b = tid; b < a.n_bins; b += kBinBlock) {
             if (lh[b]) {
                 gb[b] = atomicAdd(&a.bin_fill[b], lh[b]);
-                add_dev(&a.bin_kmers[b], (uint64_t)lk[b]);
+                tk[b] += lk[b];
             }
         }
         __syncthreads();
@@ -416,6 +419,8 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_scatter(BinArgs a) {
         }
         __syncthreads();
     }
+    for (uint32_t b = tid; b < a.n_bins; b += kBinBlock)
+        if (tk[b]) add_dev(&a.bin_kmers[b], tk[b]);
 }
 
 // Bin of each key, as the tile kernel assigns it: the smallest rank over the
@@ -481,7 +486,11 @@ hipError_t launch_bin(const BinArgs& a, uint32_t max_grid, uint32_t cus, hipStre
     hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    size_t sh_sc = 3 * (size_t)a.n_bins * sizeof(uint32_t);
+    size_t sh_sc = (3 * (size_t)a.n_bins + (a.n_bins & 1u)) * sizeof(uint32_t) + (size_t)a.n_bins * sizeof(uint64_t);
+    if (sh_sc > 65536) {   // above the default limit of dynamic LDS per workgroup (n_bins > 3276)
+        e = hipFuncSetAttribute((const void*)k_bin_scatter, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh_sc);
+        if (e != hipSuccess) return e;
+    }
     uint64_t chunks = (a.list_cap + (uint64_t)kBinBlock * kScatterPer - 1) / ((uint64_t)kBinBlock * kScatterPer);
     uint32_t g = (uint32_t)(chunks < 2048 ? (chunks ? chunks : 1) : 2048);
     hipLaunchKernelGGL(k_bin_scatter, dim3(g), dim3(kBinBlock), sh_sc, s, a);
